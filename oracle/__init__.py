@@ -1,0 +1,6 @@
+"""CPU oracle (test infrastructure only; never imported by the product path).
+
+Parity: every function is pinned by ``tests/test_oracle_pins.py``.
+"""
+from .toeplitz import (adjoint, adjoint_entries, exact_dot, forward,  # noqa: F401
+                       forward_entries, relative_l2, spectrum)
