@@ -1,0 +1,146 @@
+/*
+ * ftm.h -- C ABI of the MI355X (gfx950) FFT-based block lower-triangular
+ * Toeplitz matvec ("FFTMatvec", arXiv 2508.10202).
+ *
+ * The operator is the block lower-triangular Toeplitz matrix F of
+ * Section 2.3, eq. (ShiftInvariance): Nt x Nt blocks, each Nd x Nm, fixed by
+ * its first block column F_0 .. F_{Nt-1} (0-based lag; the paper's
+ * F_{11} .. F_{Nt,1}).  d = F m is  d_i = sum_{j<=i} F_{i-j} m_j  and the
+ * adjoint m = F^T d is  m_j = sum_{i>=j} F_{i-j}^T d_i.
+ *
+ * Both are computed by the five phases of Section 2.4: (1) zero pad every
+ * time series to L = 2 Nt, (2) batched real FFT over time, (3) per-frequency
+ * complex matrix-vector product with the precomputed spectrum
+ * Fhat_k (k = 0 .. Nt) of the zero-padded first block column (the conjugate
+ * transpose for the adjoint), (4) inverse FFT, (5) drop the padding.
+ * Each phase runs in its own precision (Section 3.2); inputs and outputs are
+ * always float64.
+ *
+ * Memory and streams
+ *   - Every array argument named as "device" is a pointer into device memory
+ *     of the current HIP device (e.g. a torch.Tensor data_ptr()); the caller
+ *     owns it.  The library never frees caller memory.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on it and return without synchronising; outputs are
+ *     valid once the stream has been synchronised.
+ *   - The library owns the spectra, twiddle tables and workspaces it
+ *     allocates; ftm_destroy_operator releases them.
+ *   - Concurrent calls on one operator must use one stream (they share the
+ *     operator's workspace) unless the serving API below is used.
+ *
+ * Errors
+ *   - Every entry point returns an ftm_status; nothing throws or aborts
+ *     across the ABI.  Argument errors are detected before any work is
+ *     enqueued.  HIP errors map to FTM_ERR_HIP.  ftm_last_error() returns a
+ *     thread-local message for the last failure on the calling thread.
+ */
+#ifndef FTM_H
+#define FTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ftm_status {
+  FTM_OK = 0,
+  FTM_ERR_INVALID = 1,     /* bad argument (null pointer, size <= 0, ...) */
+  FTM_ERR_UNSUPPORTED = 2, /* valid request this build cannot serve        */
+  FTM_ERR_OOM = 3,         /* device allocation failed                     */
+  FTM_ERR_BUDGET = 4,      /* request exceeds the serving memory budget    */
+  FTM_ERR_HIP = 5,         /* a HIP runtime call or a launch failed        */
+  FTM_ERR_STATE = 6        /* object used in a state that does not allow it */
+} ftm_status;
+
+/* Storage precision of a phase.  FP16 and BF16 phases store their data in
+ * that format and compute in float32 (accumulating in float32). */
+typedef enum ftm_dtype { FTM_F64 = 0, FTM_F32 = 1, FTM_F16 = 2, FTM_BF16 = 3 } ftm_dtype;
+
+/* Per-phase precision configuration of one direction, in execution order
+ * (Section 3.2: set when the operator is created and changeable at run
+ * time).  Phase i takes its input rounded to its own precision, computes in
+ * it (float32 for FP16/BF16) and rounds its output to it.
+ *   pad   -- phase 1, broadcast + zero padding (a memory phase)
+ *   fft   -- phase 2, real FFT of the input series
+ *   gemv  -- phase 3, storage precision of Fhat and of the product
+ *   ifft  -- phase 4, inverse real FFT
+ *   unpad -- phase 5, unpadding (a memory phase)
+ *   accum -- accumulation type of phase 3: FTM_F64 or FTM_F32.  Must be
+ *            FTM_F64 when gemv is FTM_F64 and FTM_F32 when gemv is
+ *            FTM_F16 or FTM_BF16; either for FTM_F32. */
+typedef struct ftm_precision {
+  int32_t pad, fft, gemv, ifft, unpad, accum;
+} ftm_precision;
+
+typedef struct ftm_operator_s* ftm_operator;
+
+/* Build the operator from its first block column (Section 2.4: only the first
+ * block column is stored; its zero-padded FFT along time is computed once, in
+ * float64, Section 3.2.1 "Initial state").
+ *   F        device, float64, [Nt][Nd][Nm] row-major (lag, sensor, parameter).
+ *            Only read during the call's stream work; may be freed after the
+ *            stream is synchronised.
+ *   fwd, adj precision of F and F^T matvecs; NULL means all-FP64.
+ *   spectra  bit mask (1 << ftm_dtype) of extra Fhat storage copies to keep
+ *            for later ftm_set_precision calls; the copies fwd/adj need are
+ *            always kept.
+ *   max_rhs  largest nrhs later passed to matvec/rmatvec (>= 1); sizes the
+ *            workspace.
+ * Limits: Nt in [1, 2048], Nd, Nm >= 1.  The pad length is L = 2 Nt.
+ * Returns FTM_ERR_UNSUPPORTED if L has a prime factor above 7. */
+ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd,
+                              int64_t Nm, const ftm_precision* fwd, const ftm_precision* adj,
+                              uint32_t spectra, int64_t max_rhs, void* stream);
+
+/* Change the precision configuration (NULL leaves a direction unchanged).
+ * Fails with FTM_ERR_UNSUPPORTED if the needed Fhat copy was not kept. */
+ftm_status ftm_set_precision(ftm_operator op, const ftm_precision* fwd, const ftm_precision* adj);
+
+/* d = F m for nrhs right-hand sides (Section 2.4, phases 1-5).
+ *   m device float64 [nrhs][Nt][Nm];  d device float64 [nrhs][Nt][Nd].
+ *   1 <= nrhs <= max_rhs.  m and d must not overlap. */
+ftm_status ftm_matvec(ftm_operator op, const double* m, double* d, int64_t nrhs, void* stream);
+
+/* m = F^T d for nrhs right-hand sides (Section 2.4: phase 3 uses the
+ * conjugate transpose of each Fhat_k; inputs and outputs swap).
+ *   d device float64 [nrhs][Nt][Nd];  m device float64 [nrhs][Nt][Nm]. */
+ftm_status ftm_rmatvec(ftm_operator op, const double* d, double* m, int64_t nrhs, void* stream);
+
+/* Copy bins k0 .. k0+nk-1 of the stored spectrum in storage precision
+ * `which` (widened to float64) to out: device float64 [nk][Nd][Nm][2]
+ * (real, imaginary).  Fhat_k = sum_{t<Nt} F_t exp(-2 pi i k t / L). */
+ftm_status ftm_get_spectrum(ftm_operator op, int32_t which, int64_t k0, int64_t nk, double* out,
+                            void* stream);
+
+/* Shape and memory facts: any pointer may be NULL.  device_bytes counts every
+ * device allocation the operator holds (spectra, tables, workspace). */
+ftm_status ftm_operator_info(ftm_operator op, int64_t* Nt, int64_t* Nd, int64_t* Nm, int64_t* L,
+                             size_t* device_bytes);
+
+/* Per-kernel timing (instrumentation).  While enabled, every matvec and
+ * rmatvec records HIP events on its own stream around each of its three
+ * kernels: 0 = pad + FFT (phases 1-2), 1 = product (phase 3),
+ * 2 = inverse FFT + unpad (phases 4-5).  Events come from a pool the operator
+ * owns; enabling costs one event record per kernel boundary. */
+ftm_status ftm_profile_enable(ftm_operator op, int32_t enable);
+
+/* Sum the recorded kernel times (waits for the recorded events).
+ *   ms     host double[6]: ms[dir * 3 + kernel], dir 0 = forward, 1 = adjoint
+ *   counts host int64_t[2]: number of recorded calls per direction
+ *   reset  non-zero clears the record afterwards. */
+ftm_status ftm_profile_read(ftm_operator op, double* ms, int64_t* counts, int32_t reset);
+
+/* Release everything the operator owns.  The caller must make sure no work
+ * using it is still pending.  NULL is accepted and ignored. */
+ftm_status ftm_destroy_operator(ftm_operator op);
+
+const char* ftm_status_string(ftm_status s);
+const char* ftm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTM_H */

@@ -1,0 +1,80 @@
+"""ctypes binding of ``libftm.so`` (argument marshalling only).
+
+torch is imported before the library is loaded so that the HIP runtime torch
+already holds (soname ``libamdhip64.so.7``) is the one the library binds to:
+device pointers and streams are then shared between the two.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime first, see above)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libftm.so")
+
+# ftm_status
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_BUDGET, ERR_HIP, ERR_STATE = range(7)
+# ftm_dtype
+F64, F32, F16, BF16 = range(4)
+
+# Every symbol include/ftm.h declares.
+EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
+           "ftm_get_spectrum", "ftm_operator_info", "ftm_profile_enable", "ftm_profile_read",
+           "ftm_destroy_operator",
+           "ftm_status_string", "ftm_last_error")
+
+
+class FtmPrecision(ctypes.Structure):
+    _fields_ = [("pad", ctypes.c_int32), ("fft", ctypes.c_int32), ("gemv", ctypes.c_int32),
+                ("ifft", ctypes.c_int32), ("unpad", ctypes.c_int32), ("accum", ctypes.c_int32)]
+
+
+class FtmError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func} failed: status {status} ({msg})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the library once; fails loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python paper_2508_10202_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+    prec_p = ctypes.POINTER(FtmPrecision)
+    sigs = {
+        "ftm_setup_operator": [ctypes.POINTER(vp), vp, i64, i64, i64, prec_p, prec_p, u32, i64, vp],
+        "ftm_set_precision": [vp, prec_p, prec_p],
+        "ftm_matvec": [vp, vp, vp, i64, vp],
+        "ftm_rmatvec": [vp, vp, vp, i64, vp],
+        "ftm_get_spectrum": [vp, i32, i64, i64, vp, vp],
+        "ftm_operator_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                              ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],
+        "ftm_profile_enable": [vp, i32],
+        "ftm_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32],
+        "ftm_destroy_operator": [vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.ftm_status_string.argtypes = [ctypes.c_int]
+    L.ftm_status_string.restype = ctypes.c_char_p
+    L.ftm_last_error.argtypes = []
+    L.ftm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int, func: str) -> None:
+    if status != OK:
+        L = lib()
+        raise FtmError(status, func, (L.ftm_last_error() or b"").decode())

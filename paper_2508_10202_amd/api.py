@@ -1,0 +1,201 @@
+"""Python facade over the C ABI: argument checks and marshalling only.
+
+Every step of a matvec runs in the HIP library; torch provides device memory
+(``torch.empty`` for outputs) and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+from ._lib import BF16, F16, F32, F64, FtmPrecision, check, lib
+
+_CODE = {"d": F64, "s": F32, "h": F16, "b": BF16}
+_CHAR = {v: k for k, v in _CODE.items()}
+
+
+@dataclasses.dataclass(frozen=True)
+class Precision:
+    """Per-phase precision of one direction, in execution order (Section 3.2).
+
+    Each field is one of ``F64, F32, F16, BF16``.  ``accum`` is the phase-3
+    accumulation type (``F64`` or ``F32``).
+    """
+
+    pad: int = F64
+    fft: int = F64
+    gemv: int = F64
+    ifft: int = F64
+    unpad: int = F64
+    accum: int = F64
+
+    @classmethod
+    def parse(cls, s: str) -> "Precision":
+        """``"dssdd"`` style: one of d/s/h/b per phase (pad, fft, gemv, ifft,
+        unpad), optionally ``"+a64"`` / ``"+a32"`` for the accumulation.
+        Default accumulation: FP64 for an FP64 product, FP32 otherwise."""
+        body, _, acc = s.partition("+")
+        if len(body) != 5 or any(c not in _CODE for c in body):
+            raise ValueError(f"precision string {s!r}: need 5 of d/s/h/b")
+        codes = [_CODE[c] for c in body]
+        if acc:
+            if acc not in ("a64", "a32"):
+                raise ValueError(f"precision string {s!r}: accumulation is +a64 or +a32")
+            accum = F64 if acc == "a64" else F32
+        else:
+            accum = F64 if codes[2] == F64 else F32
+        return cls(*codes, accum)
+
+    def __str__(self) -> str:
+        body = "".join(_CHAR[c] for c in (self.pad, self.fft, self.gemv, self.ifft, self.unpad))
+        default = F64 if self.gemv == F64 else F32
+        return body if self.accum == default else body + ("+a64" if self.accum == F64 else "+a32")
+
+    def c(self) -> FtmPrecision:
+        return FtmPrecision(self.pad, self.fft, self.gemv, self.ifft, self.unpad, self.accum)
+
+
+def _prec(p) -> Precision | None:
+    if p is None or isinstance(p, Precision):
+        return p
+    return Precision.parse(p)
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Operator:
+    """Block lower-triangular Toeplitz operator held on the GPU as its spectrum.
+
+    ``F`` is the first block column, a float64 CUDA tensor ``[Nt, Nd, Nm]``.
+    ``spectra`` lists extra storage formats to keep for later
+    :meth:`set_precision` calls (e.g. ``("s", "h")``).
+    """
+
+    def __init__(self, F: torch.Tensor, fwd=None, adj=None, spectra=(), max_rhs: int = 1,
+                 stream=None):
+        F = _dev_f64(F, "F")
+        if F.dim() != 3:
+            raise ValueError("F must be [Nt, Nd, Nm]")
+        self.Nt, self.Nd, self.Nm = (int(x) for x in F.shape)
+        self.device = F.device
+        self.max_rhs = int(max_rhs)
+        fwd, adj = _prec(fwd) or Precision(), _prec(adj) or Precision()
+        mask = 0
+        for s in spectra:
+            mask |= 1 << (_CODE[s] if isinstance(s, str) else int(s))
+        L = lib()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _stream_ptr(stream)
+            check(L.ftm_setup_operator(ctypes.byref(h), F.data_ptr(), self.Nt, self.Nd, self.Nm,
+                                       ctypes.byref(fwd.c()), ctypes.byref(adj.c()), mask,
+                                       self.max_rhs, st), "ftm_setup_operator")
+        self._h = h
+        self.fwd, self.adj = fwd, adj
+
+    # -- properties -------------------------------------------------------------
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise RuntimeError("operator was closed")
+        return self._h.value
+
+    def device_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(lib().ftm_operator_info(self.handle, None, None, None, None, ctypes.byref(n)),
+              "ftm_operator_info")
+        return int(n.value)
+
+    def set_precision(self, fwd=None, adj=None) -> None:
+        fwd, adj = _prec(fwd), _prec(adj)
+        check(lib().ftm_set_precision(self.handle, ctypes.byref(fwd.c()) if fwd else None,
+                                      ctypes.byref(adj.c()) if adj else None), "ftm_set_precision")
+        self.fwd, self.adj = fwd or self.fwd, adj or self.adj
+
+    # -- products -----------------------------------------------------------------
+    def _apply(self, x: torch.Tensor, adjoint: bool, out, stream) -> torch.Tensor:
+        n_in, n_out = (self.Nd, self.Nm) if adjoint else (self.Nm, self.Nd)
+        x = _dev_f64(x, "x")
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        if xb.dim() != 3 or tuple(xb.shape[1:]) != (self.Nt, n_in):
+            raise ValueError(f"input must be [nrhs,] {self.Nt} x {n_in}, got {tuple(x.shape)}")
+        nrhs = xb.shape[0]
+        if out is None:
+            out = torch.empty((nrhs, self.Nt, n_out), dtype=torch.float64, device=x.device)
+        else:
+            out = _dev_f64(out, "out")
+            if out.numel() != nrhs * self.Nt * n_out:
+                raise ValueError("out has the wrong size")
+        fn = lib().ftm_rmatvec if adjoint else lib().ftm_matvec
+        with torch.cuda.device(x.device):
+            check(fn(self.handle, xb.data_ptr(), out.data_ptr(), nrhs, _stream_ptr(stream)),
+                  "ftm_rmatvec" if adjoint else "ftm_matvec")
+        return out[0] if single and out.dim() == 3 else out
+
+    def matvec(self, m: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """``d = F m``; ``m`` is ``[Nt, Nm]`` or ``[nrhs, Nt, Nm]``."""
+        return self._apply(m, False, out, stream)
+
+    def rmatvec(self, d: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """``m = F^T d``; ``d`` is ``[Nt, Nd]`` or ``[nrhs, Nt, Nd]``."""
+        return self._apply(d, True, out, stream)
+
+    def spectrum(self, which="d", k0: int = 0, nk: int | None = None, stream=None) -> torch.Tensor:
+        """Stored ``Fhat_k`` for ``k0 <= k < k0 + nk`` as complex128 ``[nk, Nd, Nm]``."""
+        nk = (self.Nt + 1 - k0) if nk is None else nk
+        code = _CODE[which] if isinstance(which, str) else int(which)
+        out = torch.empty((nk, self.Nd, self.Nm, 2), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            check(lib().ftm_get_spectrum(self.handle, code, k0, nk, out.data_ptr(), _stream_ptr(stream)),
+                  "ftm_get_spectrum")
+        return torch.view_as_complex(out)
+
+    def profile(self, enable: bool = True) -> None:
+        """Record HIP events around each kernel of every following call."""
+        check(lib().ftm_profile_enable(self.handle, 1 if enable else 0), "ftm_profile_enable")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """Average kernel times in ms: {"fwd": [fft, product, ifft], "adj": [...], "n": (nf, na)}."""
+        ms = (ctypes.c_double * 6)()
+        cnt = (ctypes.c_int64 * 2)()
+        check(lib().ftm_profile_read(self.handle, ms, cnt, 1 if reset else 0), "ftm_profile_read")
+        out = {"n": (int(cnt[0]), int(cnt[1]))}
+        for d, name in enumerate(("fwd", "adj")):
+            n = max(int(cnt[d]), 1)
+            out[name] = [ms[3 * d + i] / n for i in range(3)]
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().ftm_destroy_operator(self._h.value)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

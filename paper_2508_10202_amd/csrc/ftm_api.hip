@@ -1,0 +1,529 @@
+// Host runtime behind the C ABI of include/ftm.h: operator setup (the one-time
+// float64 transform of the first block column, Section 2.4 and Section 3.2.1
+// "Initial state"), per-phase precision dispatch (Section 3.2), workspace and
+// the stream-ordered three-kernel chain of a matvec.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ftm.h"
+#include "ftm_device.h"
+#include "ftm_kernels.h"
+
+using namespace ftm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ftm_status fail(ftm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+ftm_status fail_hip(const char* what, hipError_t e) {
+  return fail(FTM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FTM_HIP(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return fail_hip(#expr, e_);  \
+  } while (0)
+
+size_t dtype_bytes(int dt) {  // bytes of one complex number in storage format dt
+  switch (dt) {
+    case DT_F64: return 16;
+    case DT_F32: return 8;
+    default: return 4;
+  }
+}
+
+bool valid_dtype(int32_t v) { return v >= DT_F64 && v <= DT_BF16; }
+
+ftm_status check_precision(const ftm_precision& p) {
+  if (!valid_dtype(p.pad) || !valid_dtype(p.fft) || !valid_dtype(p.gemv) || !valid_dtype(p.ifft) ||
+      !valid_dtype(p.unpad))
+    return fail(FTM_ERR_INVALID, "precision: every phase must be FTM_F64, FTM_F32, FTM_F16 or FTM_BF16");
+  if (p.accum != DT_F64 && p.accum != DT_F32)
+    return fail(FTM_ERR_INVALID, "precision: accum must be FTM_F64 or FTM_F32");
+  if (p.gemv == DT_F64 && p.accum != DT_F64)
+    return fail(FTM_ERR_INVALID, "precision: an FP64 product accumulates in FP64");
+  if ((p.gemv == DT_F16 || p.gemv == DT_BF16) && p.accum != DT_F32)
+    return fail(FTM_ERR_INVALID, "precision: FP16/BF16 products accumulate in FP32");
+  return FTM_OK;
+}
+
+const ftm_precision kAllF64 = {DT_F64, DT_F64, DT_F64, DT_F64, DT_F64, DT_F64};
+
+// Radices of a length-N plan: powers of two in radix-8 passes (a radix-4 pair
+// or one radix-4/radix-2 pass takes the remainder), then 5, 3 and 7.
+bool make_plan(int N, FftPlan* plan) {
+  int n = N, e2 = 0;
+  std::vector<int> rad;
+  while (n % 2 == 0) { n /= 2; ++e2; }
+  if (e2 % 3 == 1 && e2 >= 4) { rad.push_back(4); rad.push_back(4); e2 -= 4; }
+  while (e2 >= 3) { rad.push_back(8); e2 -= 3; }
+  if (e2 == 2) rad.push_back(4);
+  if (e2 == 1) rad.push_back(2);
+  for (int r : {5, 3, 7})
+    while (n % r == 0) { n /= r; rad.push_back(r); }
+  if (n != 1 || (int)rad.size() > MAX_STAGES) return false;
+  plan->N = N;
+  plan->nst = (int)rad.size();
+  for (int i = 0; i < plan->nst; ++i) plan->rad[i] = rad[i];
+  return true;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct ftm_operator_s {
+  int64_t Nt = 0, Nd = 0, Nm = 0, L = 0, K = 0;
+  int ldm = 0, ldd = 0;  // padded column counts of spectra and workspaces
+  int device = 0;
+  int64_t max_rhs = 1;
+  FftPlan plan{};
+  DevBuf tw64, tw32;       // exp(-2 pi i e / L), e = 0 .. L-1
+  DevBuf spec[4];          // Fhat[K][Nd][ldm] per storage format
+  DevBuf mhat, dhat;       // [K][max_rhs][ldm], [K][max_rhs][ldd] complex (float64-sized)
+  ftm_precision fwd = kAllF64, adj = kAllF64;
+
+  // instrumentation: events around the three kernels of each recorded call
+  bool profiling = false;
+  struct Rec {
+    int dir;
+    hipEvent_t ev[4];
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+
+  size_t bytes() const {
+    size_t b = tw64.n + tw32.n + mhat.n + dhat.n;
+    for (const auto& s : spec) b += s.n;
+    return b;
+  }
+};
+
+namespace {
+
+ftm_status dev_alloc(DevBuf* b, size_t n) {
+  b->n = 0;
+  hipError_t e = hipMalloc(&b->p, n ? n : 1);
+  if (e != hipSuccess) {
+    b->p = nullptr;
+    (void)hipGetLastError();
+    return fail(FTM_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e));
+  }
+  b->n = n;
+  return FTM_OK;
+}
+
+void dev_free(DevBuf* b) {
+  if (b->p) (void)hipFree(b->p);
+  b->p = nullptr;
+  b->n = 0;
+}
+
+void release(ftm_operator op) {
+  for (auto& r : op->recs)
+    for (hipEvent_t e : r.ev) op->event_pool.push_back(e);
+  op->recs.clear();
+  for (hipEvent_t e : op->event_pool) (void)hipEventDestroy(e);
+  op->event_pool.clear();
+  dev_free(&op->tw64);
+  dev_free(&op->tw32);
+  for (auto& s : op->spec) dev_free(&s);
+  dev_free(&op->mhat);
+  dev_free(&op->dhat);
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old_) == hipSuccess && old_ != dev) {
+      if (hipSetDevice(dev) == hipSuccess) switched_ = true;
+    }
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(old_);
+  }
+
+ private:
+  int old_ = 0;
+  bool switched_ = false;
+};
+
+// Twiddle tables exp(-2 pi i e / L), evaluated in long double and rounded once.
+ftm_status upload_twiddles(ftm_operator op, hipStream_t st) {
+  const int64_t L = op->L;
+  std::vector<double> t64(2 * L);
+  std::vector<float> t32(2 * L);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int64_t e = 0; e < L; ++e) {
+    const long double ang = two_pi * (long double)e / (long double)L;
+    const long double c = cosl(ang), s = -sinl(ang);
+    t64[2 * e] = (double)c;
+    t64[2 * e + 1] = (double)s;
+    t32[2 * e] = (float)c;
+    t32[2 * e + 1] = (float)s;
+  }
+  ftm_status s;
+  if ((s = dev_alloc(&op->tw64, t64.size() * sizeof(double))) != FTM_OK) return s;
+  if ((s = dev_alloc(&op->tw32, t32.size() * sizeof(float))) != FTM_OK) return s;
+  FTM_HIP(hipMemcpyAsync(op->tw64.p, t64.data(), op->tw64.n, hipMemcpyHostToDevice, st));
+  FTM_HIP(hipMemcpyAsync(op->tw32.p, t32.data(), op->tw32.n, hipMemcpyHostToDevice, st));
+  // the host vectors die at return: make the copies complete first
+  FTM_HIP(hipStreamSynchronize(st));
+  return FTM_OK;
+}
+
+// Make sure the spectrum copies the two configurations (and `mask`) need
+// exist, creating them from the float64 spectrum.
+ftm_status ensure_spectra(ftm_operator op, uint32_t mask, hipStream_t st) {
+  const int64_t n = op->K * op->Nd * op->ldm;
+  for (int dt = DT_F32; dt <= DT_BF16; ++dt) {
+    if (!(mask & (1u << dt)) || op->spec[dt].p) continue;
+    if (!op->spec[DT_F64].p)
+      return fail(FTM_ERR_UNSUPPORTED, "spectrum in format " + std::to_string(dt) +
+                                           " was not kept at setup and the FP64 spectrum is gone");
+    ftm_status s = dev_alloc(&op->spec[dt], (size_t)n * dtype_bytes(dt));
+    if (s != FTM_OK) return s;
+    FTM_HIP(launch_store_spectrum(op->spec[DT_F64].p, dt, op->spec[dt].p, n, st));
+  }
+  return FTM_OK;
+}
+
+// Record event i of the current profiled call (no-op when not profiling).
+struct Profiler {
+  ftm_operator op;
+  hipStream_t st;
+  ftm_operator_s::Rec* rec = nullptr;
+  Profiler(ftm_operator o, hipStream_t s, int dir) : op(o), st(s) {
+    if (!op->profiling) return;
+    ftm_operator_s::Rec r{};
+    r.dir = dir;
+    for (auto& e : r.ev) {
+      if (!op->event_pool.empty()) {
+        e = op->event_pool.back();
+        op->event_pool.pop_back();
+      } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+      }
+    }
+    op->recs.push_back(r);
+    rec = &op->recs.back();
+  }
+  void mark(int i) {
+    if (rec && rec->ev[i]) (void)hipEventRecord(rec->ev[i], st);
+  }
+};
+
+// One direction of the matvec: x (float64, [nrhs][Nt][Sx]) -> y (float64,
+// [nrhs][Nt][Sy]).  adjoint selects Fhat^H in phase 3.
+ftm_status run_matvec(ftm_operator op, bool adjoint, const double* x, double* y, int64_t nrhs,
+                      hipStream_t st) {
+  const ftm_precision& p = adjoint ? op->adj : op->fwd;
+  const void* F = op->spec[p.gemv].p;
+  if (!F) return fail(FTM_ERR_STATE, "spectrum for the configured phase-3 precision is missing");
+
+  // Intermediates between phases are stored in float64 only when both
+  // neighbouring phases are float64; otherwise the producing kernel applies
+  // both phases' roundings and stores float32, which holds every such value
+  // exactly (FP16 and BF16 values are float32 values).
+  const bool x_hat64 = p.fft == DT_F64 && p.gemv == DT_F64;
+  const bool y_hat64 = p.gemv == DT_F64 && p.ifft == DT_F64;
+  const int64_t Sx = adjoint ? op->Nd : op->Nm, Sy = adjoint ? op->Nm : op->Nd;
+  const int ldx = adjoint ? op->ldd : op->ldm, ldy = adjoint ? op->ldm : op->ldd;
+  void* xhat = adjoint ? op->dhat.p : op->mhat.p;
+  void* yhat = adjoint ? op->mhat.p : op->dhat.p;
+
+  RfftArgs ra{};
+  ra.x = x;
+  ra.x_rhs_stride = op->Nt * Sx;
+  ra.x_row_stride = Sx;
+  ra.S = Sx;
+  ra.Nt = (int)op->Nt;
+  ra.nrhs = (int)nrhs;
+  ra.out = xhat;
+  ra.out_k_stride = nrhs * ldx;
+  ra.out_rhs_stride = ldx;
+  ra.ncol = Sx;
+  ra.ld_row = ldx;
+  ra.r_pad = p.pad;
+  ra.r_fft = p.fft;
+  ra.r_next = p.gemv;
+  const void* tw_in = p.fft == DT_F64 ? op->tw64.p : op->tw32.p;
+  Profiler prof(op, st, adjoint ? 1 : 0);
+  prof.mark(0);
+  FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, op->plan, tw_in, st));
+
+  GemvArgs ga{};
+  ga.F = F;
+  ga.f_k_stride = op->Nd * op->ldm;
+  ga.ld = op->ldm;
+  ga.Nd = (int)op->Nd;
+  ga.Nm = (int)op->Nm;
+  ga.K = (int)op->K;
+  ga.nrhs = (int)nrhs;
+  ga.x = xhat;
+  ga.x_k_stride = nrhs * ldx;
+  ga.x_rhs_stride = ldx;
+  ga.y = yhat;
+  ga.y_k_stride = nrhs * ldy;
+  ga.y_rhs_stride = ldy;
+  ga.r_gemv = p.gemv;
+  ga.r_next = p.ifft;
+  const bool acc64 = p.accum == DT_F64;
+  prof.mark(1);
+  if (adjoint) FTM_HIP(launch_gemv_adj(p.gemv, acc64, x_hat64, y_hat64, ga, st));
+  else FTM_HIP(launch_gemv_fwd(p.gemv, acc64, x_hat64, y_hat64, ga, st));
+
+  IrfftArgs ia{};
+  ia.in = yhat;
+  ia.in_k_stride = nrhs * ldy;
+  ia.in_rhs_stride = ldy;
+  ia.S = Sy;
+  ia.Nt = (int)op->Nt;
+  ia.nrhs = (int)nrhs;
+  ia.y = y;
+  ia.y_rhs_stride = op->Nt * Sy;
+  ia.y_row_stride = Sy;
+  ia.r_ifft = p.ifft;
+  ia.r_unpad = p.unpad;
+  const void* tw_out = p.ifft == DT_F64 ? op->tw64.p : op->tw32.p;
+  prof.mark(2);
+  FTM_HIP(launch_irfft(y_hat64, p.ifft == DT_F64, ia, op->plan, tw_out, st));
+  prof.mark(3);
+  return FTM_OK;
+}
+
+uint32_t needed_mask(const ftm_precision& f, const ftm_precision& a) { return (1u << f.gemv) | (1u << a.gemv); }
+
+}  // namespace
+
+extern "C" {
+
+const char* ftm_status_string(ftm_status s) {
+  switch (s) {
+    case FTM_OK: return "ok";
+    case FTM_ERR_INVALID: return "invalid argument";
+    case FTM_ERR_UNSUPPORTED: return "unsupported";
+    case FTM_ERR_OOM: return "out of device memory";
+    case FTM_ERR_BUDGET: return "over memory budget";
+    case FTM_ERR_HIP: return "HIP error";
+    case FTM_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* ftm_last_error(void) { return g_last_error.c_str(); }
+
+ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd, int64_t Nm,
+                              const ftm_precision* fwd, const ftm_precision* adj, uint32_t spectra,
+                              int64_t max_rhs, void* stream) {
+  try {
+    if (!out) return fail(FTM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!F) return fail(FTM_ERR_INVALID, "F is NULL");
+    if (Nt < 1 || Nd < 1 || Nm < 1 || max_rhs < 1)
+      return fail(FTM_ERR_INVALID, "Nt, Nd, Nm and max_rhs must be >= 1");
+    if (2 * Nt > FFT_POINTS)
+      return fail(FTM_ERR_UNSUPPORTED, "Nt above " + std::to_string(FFT_POINTS / 2) + " is not supported");
+    if (Nd > (1 << 24) || Nm > (1 << 24) || Nd * Nm > ((int64_t)1 << 34) || max_rhs > (1 << 20))
+      return fail(FTM_ERR_UNSUPPORTED, "size too large");
+    if (spectra >> 4) return fail(FTM_ERR_INVALID, "spectra mask has bits beyond FTM_BF16");
+    const ftm_precision pf = fwd ? *fwd : kAllF64, pa = adj ? *adj : kAllF64;
+    ftm_status s;
+    if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
+
+    FftPlan plan{};
+    if (!make_plan((int)(2 * Nt), &plan))
+      return fail(FTM_ERR_UNSUPPORTED, "2*Nt must factor into 2, 3, 5 and 7");
+
+    ftm_operator op = new ftm_operator_s();
+    op->Nt = Nt;
+    op->Nd = Nd;
+    op->Nm = Nm;
+    op->L = 2 * Nt;
+    op->K = Nt + 1;
+    op->ldm = (int)((Nm + 7) / 8 * 8);
+    op->ldd = (int)((Nd + 7) / 8 * 8);
+    op->max_rhs = max_rhs;
+    op->plan = plan;
+    op->fwd = pf;
+    op->adj = pa;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    auto bail = [&](ftm_status e) {
+      (void)hipStreamSynchronize(st);
+      release(op);
+      delete op;
+      return e;
+    };
+    if (hipGetDevice(&op->device) != hipSuccess) return bail(fail(FTM_ERR_HIP, "hipGetDevice failed"));
+    if ((s = upload_twiddles(op, st)) != FTM_OK) return bail(s);
+
+    // Fhat in float64: transform every (r, c) series of F along time.
+    const int64_t nspec = op->K * Nd * op->ldm;
+    if ((s = dev_alloc(&op->spec[DT_F64], (size_t)nspec * 16)) != FTM_OK) return bail(s);
+    hipError_t e = hipMemsetAsync(op->spec[DT_F64].p, 0, op->spec[DT_F64].n, st);
+    if (e != hipSuccess) return bail(fail_hip("hipMemsetAsync", e));
+    RfftArgs ra{};
+    ra.x = F;
+    ra.x_rhs_stride = 0;
+    ra.x_row_stride = Nd * Nm;
+    ra.S = Nd * Nm;
+    ra.Nt = (int)Nt;
+    ra.nrhs = 1;
+    ra.out = op->spec[DT_F64].p;
+    ra.out_k_stride = Nd * op->ldm;
+    ra.out_rhs_stride = 0;
+    ra.ncol = Nm;
+    ra.ld_row = op->ldm;
+    ra.r_pad = ra.r_fft = ra.r_next = DT_F64;
+    e = launch_rfft(true, true, ra, op->plan, op->tw64.p, st);
+    if (e != hipSuccess) return bail(fail_hip("setup transform", e));
+
+    const uint32_t keep = needed_mask(pf, pa) | spectra;
+    if ((s = ensure_spectra(op, keep, st)) != FTM_OK) return bail(s);
+
+    const size_t ws_m = (size_t)op->K * max_rhs * op->ldm * 16, ws_d = (size_t)op->K * max_rhs * op->ldd * 16;
+    if ((s = dev_alloc(&op->mhat, ws_m)) != FTM_OK) return bail(s);
+    if ((s = dev_alloc(&op->dhat, ws_d)) != FTM_OK) return bail(s);
+    // padding columns of the workspaces are read (times zero) and must stay finite
+    if ((e = hipMemsetAsync(op->mhat.p, 0, ws_m, st)) != hipSuccess) return bail(fail_hip("hipMemsetAsync", e));
+    if ((e = hipMemsetAsync(op->dhat.p, 0, ws_d, st)) != hipSuccess) return bail(fail_hip("hipMemsetAsync", e));
+
+    if (!(keep & (1u << DT_F64))) {
+      // the copies were made on this stream; wait before freeing their source
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(fail_hip("hipStreamSynchronize", e));
+      dev_free(&op->spec[DT_F64]);
+    }
+    *out = op;
+    return FTM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FTM_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(FTM_ERR_INVALID, "unexpected exception in ftm_setup_operator");
+  }
+}
+
+ftm_status ftm_set_precision(ftm_operator op, const ftm_precision* fwd, const ftm_precision* adj) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  const ftm_precision pf = fwd ? *fwd : op->fwd, pa = adj ? *adj : op->adj;
+  ftm_status s;
+  if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
+  if (!op->spec[pf.gemv].p || !op->spec[pa.gemv].p)
+    return fail(FTM_ERR_UNSUPPORTED, "the spectrum copy this configuration needs was not kept at setup");
+  op->fwd = pf;
+  op->adj = pa;
+  return FTM_OK;
+}
+
+static ftm_status matvec_common(ftm_operator op, bool adjoint, const double* x, double* y, int64_t nrhs,
+                                void* stream) {
+  try {
+    if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+    if (!x || !y) return fail(FTM_ERR_INVALID, "input or output is NULL");
+    if (nrhs < 1 || nrhs > op->max_rhs)
+      return fail(FTM_ERR_INVALID, "nrhs must be in [1, max_rhs=" + std::to_string(op->max_rhs) + "]");
+    const int64_t nx = nrhs * op->Nt * (adjoint ? op->Nd : op->Nm);
+    const int64_t ny = nrhs * op->Nt * (adjoint ? op->Nm : op->Nd);
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* yb = reinterpret_cast<const char*>(y);
+    if (xb < yb + ny * 8 && yb < xb + nx * 8) return fail(FTM_ERR_INVALID, "input and output overlap");
+    DeviceGuard g(op->device);
+    return run_matvec(op, adjoint, x, y, nrhs, reinterpret_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(FTM_ERR_INVALID, "unexpected exception in matvec");
+  }
+}
+
+ftm_status ftm_matvec(ftm_operator op, const double* m, double* d, int64_t nrhs, void* stream) {
+  return matvec_common(op, false, m, d, nrhs, stream);
+}
+
+ftm_status ftm_rmatvec(ftm_operator op, const double* d, double* m, int64_t nrhs, void* stream) {
+  return matvec_common(op, true, d, m, nrhs, stream);
+}
+
+ftm_status ftm_get_spectrum(ftm_operator op, int32_t which, int64_t k0, int64_t nk, double* out, void* stream) {
+  if (!op || !out) return fail(FTM_ERR_INVALID, "operator or out is NULL");
+  if (!valid_dtype(which)) return fail(FTM_ERR_INVALID, "which must be an ftm_dtype");
+  if (k0 < 0 || nk < 1 || k0 + nk > op->K) return fail(FTM_ERR_INVALID, "bins out of range");
+  if (!op->spec[which].p) return fail(FTM_ERR_UNSUPPORTED, "no spectrum stored in that format");
+  DeviceGuard g(op->device);
+  const char* src = reinterpret_cast<const char*>(op->spec[which].p) +
+                    (size_t)k0 * op->Nd * op->ldm * dtype_bytes(which);
+  FTM_HIP(launch_widen_spectrum(src, which, out, nk * op->Nd, op->Nm, op->ldm,
+                                reinterpret_cast<hipStream_t>(stream)));
+  return FTM_OK;
+}
+
+ftm_status ftm_operator_info(ftm_operator op, int64_t* Nt, int64_t* Nd, int64_t* Nm, int64_t* L,
+                             size_t* device_bytes) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (Nt) *Nt = op->Nt;
+  if (Nd) *Nd = op->Nd;
+  if (Nm) *Nm = op->Nm;
+  if (L) *L = op->L;
+  if (device_bytes) *device_bytes = op->bytes();
+  return FTM_OK;
+}
+
+ftm_status ftm_profile_enable(ftm_operator op, int32_t enable) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  op->profiling = enable != 0;
+  return FTM_OK;
+}
+
+ftm_status ftm_profile_read(ftm_operator op, double* ms, int64_t* counts, int32_t reset) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  int64_t cnt[2] = {0, 0};
+  DeviceGuard g(op->device);
+  for (const auto& r : op->recs) {
+    bool ok = true;
+    for (hipEvent_t e : r.ev) ok = ok && e != nullptr;
+    if (!ok) continue;
+    FTM_HIP(hipEventSynchronize(r.ev[3]));
+    for (int i = 0; i < 3; ++i) {
+      float t = 0.f;
+      FTM_HIP(hipEventElapsedTime(&t, r.ev[i], r.ev[i + 1]));
+      acc[r.dir * 3 + i] += t;
+    }
+    cnt[r.dir] += 1;
+  }
+  if (ms)
+    for (int i = 0; i < 6; ++i) ms[i] = acc[i];
+  if (counts) {
+    counts[0] = cnt[0];
+    counts[1] = cnt[1];
+  }
+  if (reset) {
+    for (auto& r : op->recs)
+      for (hipEvent_t e : r.ev)
+        if (e) op->event_pool.push_back(e);
+    op->recs.clear();
+  }
+  return FTM_OK;
+}
+
+ftm_status ftm_destroy_operator(ftm_operator op) {
+  if (!op) return FTM_OK;
+  DeviceGuard g(op->device);
+  release(op);
+  delete op;
+  return FTM_OK;
+}
+
+}  // extern "C"

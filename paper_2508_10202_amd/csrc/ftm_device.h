@@ -1,0 +1,164 @@
+// Device-side helpers shared by the FFT and GEMV kernels: complex arithmetic,
+// the storage formats of each precision, round-to-nearest-even into a format,
+// and the XCD-aware workgroup order used by every streaming kernel.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ftm {
+
+enum : int { DT_F64 = 0, DT_F32 = 1, DT_F16 = 2, DT_BF16 = 3 };
+
+template <class T>
+struct alignas(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <class T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// -i * a  (multiplication by the forward-transform quarter turn)
+template <class T>
+__device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) { return {a.y, -a.x}; }
+template <class T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------------------
+// Round-to-nearest-even into a binary format with p significand bits (the
+// implicit bit included), smallest normal exponent emin and largest finite
+// value maxv.  Values below the normal range are rounded on the subnormal
+// grid 2^(emin-p+1); values that round beyond maxv become infinities.  The
+// scaling by the quantum q is exact (q is a power of two and x/q stays well
+// inside the double range), and rint rounds half-way cases to even.
+__device__ __forceinline__ double round_fmt(double x, int p, int emin, double maxv) {
+  const double ax = fabs(x);
+  if (!(ax > 0.0) || isinf(ax)) return x;
+  int e = ilogb(ax);
+  if (e < emin) e = emin;
+  const double q = ldexp(1.0, e - p + 1);
+  double r = rint(x / q) * q;
+  if (fabs(r) > maxv) r = copysign(__builtin_inf(), x);
+  return r;
+}
+__device__ __forceinline__ float round_fmt(float x, int p, int emin, float maxv) {
+  const float ax = fabsf(x);
+  if (!(ax > 0.0f) || isinf(ax)) return x;
+  int e = ilogbf(ax);
+  if (e < emin) e = emin;
+  const float q = ldexpf(1.0f, e - p + 1);
+  float r = rintf(x / q) * q;
+  if (fabsf(r) > maxv) r = copysignf(__builtin_inff(), x);
+  return r;
+}
+
+constexpr double F16_MAX = 65504.0;
+constexpr double BF16_MAX = 3.38953138925153547590470800371487866880e+38;
+
+// Value of x after storage in format dt (a value of the same C type).
+__device__ __forceinline__ double round_to(double x, int dt) {
+  switch (dt) {
+    case DT_F32: return (double)(float)x;
+    case DT_F16: return round_fmt(x, 11, -14, F16_MAX);
+    case DT_BF16: return round_fmt(x, 8, -126, BF16_MAX);
+    default: return x;
+  }
+}
+__device__ __forceinline__ float round_to(float x, int dt) {
+  switch (dt) {
+    case DT_F16: return round_fmt(x, 11, -14, (float)F16_MAX);
+    case DT_BF16: return round_fmt(x, 8, -126, (float)BF16_MAX);
+    default: return x;
+  }
+}
+template <class T>
+__device__ __forceinline__ cplx<T> round_to(cplx<T> a, int dt) {
+  return {round_to(a.x, dt), round_to(a.y, dt)};
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats of the spectrum.  Each tag names the element stored per
+// complex number and how many complex numbers one 16-byte load carries.
+struct s_f64 {
+  using elem = cplx<double>;
+  static constexpr int V = 1;
+};
+struct s_f32 {
+  using elem = cplx<float>;
+  static constexpr int V = 2;
+};
+struct h2 {
+  uint16_t x, y;
+};
+struct s_f16 {
+  using elem = h2;
+  static constexpr int V = 4;
+};
+struct s_bf16 {
+  using elem = h2;
+  static constexpr int V = 4;
+};
+
+__device__ __forceinline__ float half_bits_to_float(uint16_t b) {
+  return __half2float(__ushort_as_half(b));
+}
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Decode the V complex numbers of one 16-byte chunk into accumulation type TA.
+template <class S, class TA>
+struct Chunk;
+
+template <class TA>
+struct Chunk<s_f64, TA> {
+  static __device__ __forceinline__ void decode(const uint4& u, cplx<TA>* out) {
+    const double2 d = *reinterpret_cast<const double2*>(&u);
+    out[0] = {(TA)d.x, (TA)d.y};
+  }
+};
+template <class TA>
+struct Chunk<s_f32, TA> {
+  static __device__ __forceinline__ void decode(const uint4& u, cplx<TA>* out) {
+    out[0] = {(TA)__uint_as_float(u.x), (TA)__uint_as_float(u.y)};
+    out[1] = {(TA)__uint_as_float(u.z), (TA)__uint_as_float(u.w)};
+  }
+};
+template <class TA>
+struct Chunk<s_f16, TA> {
+  static __device__ __forceinline__ void decode(const uint4& u, cplx<TA>* out) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      out[i] = {(TA)half_bits_to_float(w[i] & 0xffffu), (TA)half_bits_to_float(w[i] >> 16)};
+  }
+};
+template <class TA>
+struct Chunk<s_bf16, TA> {
+  static __device__ __forceinline__ void decode(const uint4& u, cplx<TA>* out) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      out[i] = {(TA)__uint_as_float(w[i] << 16), (TA)__uint_as_float(w[i] & 0xffff0000u)};
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Workgroups are handed to the 8 XCDs round robin (workgroup i runs on XCD
+// i mod 8).  Re-number them so that each XCD works through one contiguous
+// range of logical workgroup ids: neighbouring tiles, which share input
+// vectors, then meet in the same XCD's L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_order(int i, int n) {
+  const int xcd = i % NUM_XCD, local = i / NUM_XCD;
+  const int base = n / NUM_XCD, rem = n % NUM_XCD;
+  return xcd < rem ? xcd * (base + 1) + local : rem * (base + 1) + (xcd - rem) * base + local;
+}
+
+}  // namespace ftm

@@ -1,0 +1,326 @@
+// Batched real FFTs over time with the zero padding (phases 1+2) and the
+// unpadding (phases 4+5) fused in, for gfx950.
+//
+// Each workgroup holds P complex series of length N = L in LDS and runs a
+// mixed-radix (2, 3, 4, 5, 7, 8) self-sorting Stockham FFT on them: every
+// pass reads R points at stride N/R, applies the twiddles, does an R-point
+// DFT in registers and writes the results back in sorted order (the
+// formulation of Govindaraju et al., SC'08).  Two real series share one
+// complex transform (real part / imaginary part) and are separated with the
+// conjugate symmetry of real spectra afterwards, so P complex series carry 2P
+// of the caller's real series.  Twiddles come from a table computed on the
+// host in long double.
+#include "ftm_device.h"
+#include "ftm_kernels.h"
+
+namespace ftm {
+
+// ---- R-point DFTs, forward sign exp(-2 pi i jk / R) --------------------------
+
+template <class T>
+__device__ __forceinline__ void dft2(cplx<T>* a) {
+  const cplx<T> t = a[1];
+  a[1] = csub(a[0], t);
+  a[0] = cadd(a[0], t);
+}
+
+template <class T>
+__device__ __forceinline__ void dft3(cplx<T>* a) {
+  const T s3 = (T)0.8660254037844386467637232;  // sin(pi/3)
+  const cplx<T> t = cadd(a[1], a[2]);
+  const cplx<T> d = cscale(csub(a[1], a[2]), s3);
+  const cplx<T> m = {a[0].x - (T)0.5 * t.x, a[0].y - (T)0.5 * t.y};
+  a[0] = cadd(a[0], t);
+  a[1] = cadd(m, mul_mi(d));
+  a[2] = csub(m, mul_mi(d));
+}
+
+template <class T>
+__device__ __forceinline__ void dft4(cplx<T>* a) {
+  const cplx<T> t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+  const cplx<T> t2 = cadd(a[1], a[3]), t3 = mul_mi(csub(a[1], a[3]));
+  a[0] = cadd(t0, t2);
+  a[2] = csub(t0, t2);
+  a[1] = cadd(t1, t3);
+  a[3] = csub(t1, t3);
+}
+
+template <class T>
+__device__ __forceinline__ void dft5(cplx<T>* a) {
+  const T c1 = (T)0.3090169943749474241022934, c2 = (T)-0.8090169943749474241022934;
+  const T s1 = (T)0.9510565162951535721164393, s2 = (T)0.5877852522924731291687059;
+  const cplx<T> t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+  const cplx<T> d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+  const cplx<T> b1 = {a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y};
+  const cplx<T> b2 = {a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y};
+  const cplx<T> e1 = {s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
+  const cplx<T> e2 = {s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
+  a[0] = cadd(a[0], cadd(t1, t2));
+  a[1] = cadd(b1, mul_mi(e1));
+  a[4] = csub(b1, mul_mi(e1));
+  a[2] = cadd(b2, mul_mi(e2));
+  a[3] = csub(b2, mul_mi(e2));
+}
+
+template <class T>
+__device__ __forceinline__ void dft7(cplx<T>* a) {
+  const T C1 = (T)0.6234898018587335305250049, C2 = (T)-0.2225209339563144042889026,
+          C3 = (T)-0.9009688679024191262361023;
+  const T S1 = (T)0.7818314824680298087084445, S2 = (T)0.9749279121818236070181317,
+          S3 = (T)0.4338837391175581204757683;
+  const cplx<T> t1 = cadd(a[1], a[6]), t2 = cadd(a[2], a[5]), t3 = cadd(a[3], a[4]);
+  const cplx<T> d1 = csub(a[1], a[6]), d2 = csub(a[2], a[5]), d3 = csub(a[3], a[4]);
+  const cplx<T> x0 = a[0];
+  // cos(2 pi jk/7) and sin(2 pi jk/7) for j = 1..3 at k = 1, 2, 3
+  const cplx<T> b1 = {x0.x + C1 * t1.x + C2 * t2.x + C3 * t3.x, x0.y + C1 * t1.y + C2 * t2.y + C3 * t3.y};
+  const cplx<T> b2 = {x0.x + C2 * t1.x + C3 * t2.x + C1 * t3.x, x0.y + C2 * t1.y + C3 * t2.y + C1 * t3.y};
+  const cplx<T> b3 = {x0.x + C3 * t1.x + C1 * t2.x + C2 * t3.x, x0.y + C3 * t1.y + C1 * t2.y + C2 * t3.y};
+  const cplx<T> e1 = {S1 * d1.x + S2 * d2.x + S3 * d3.x, S1 * d1.y + S2 * d2.y + S3 * d3.y};
+  const cplx<T> e2 = {S2 * d1.x - S3 * d2.x - S1 * d3.x, S2 * d1.y - S3 * d2.y - S1 * d3.y};
+  const cplx<T> e3 = {S3 * d1.x - S1 * d2.x + S2 * d3.x, S3 * d1.y - S1 * d2.y + S2 * d3.y};
+  a[0] = cadd(x0, cadd(t1, cadd(t2, t3)));
+  a[1] = cadd(b1, mul_mi(e1));
+  a[6] = csub(b1, mul_mi(e1));
+  a[2] = cadd(b2, mul_mi(e2));
+  a[5] = csub(b2, mul_mi(e2));
+  a[3] = cadd(b3, mul_mi(e3));
+  a[4] = csub(b3, mul_mi(e3));
+}
+
+template <class T>
+__device__ __forceinline__ void dft8(cplx<T>* a) {
+  const T h = (T)0.7071067811865475244008444;  // sqrt(1/2)
+  cplx<T> e[4] = {a[0], a[2], a[4], a[6]};
+  cplx<T> o[4] = {a[1], a[3], a[5], a[7]};
+  dft4(e);
+  dft4(o);
+  // o[k] *= exp(-2 pi i k / 8)
+  o[1] = {h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};
+  o[2] = mul_mi(o[2]);
+  o[3] = {h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = cadd(e[k], o[k]);
+    a[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <int R, class T>
+__device__ __forceinline__ void dft(cplx<T>* a) {
+  if constexpr (R == 2) dft2(a);
+  else if constexpr (R == 3) dft3(a);
+  else if constexpr (R == 4) dft4(a);
+  else if constexpr (R == 5) dft5(a);
+  else if constexpr (R == 7) dft7(a);
+  else dft8(a);
+}
+
+// One Stockham pass of radix R over P series of length N held in LDS.
+// Ns is the product of the radices of the earlier passes.  All reads of the
+// pass complete (barrier) before any write, so the pass works in place.
+template <int R, class T>
+__device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
+                                         const cplx<T>* __restrict__ tw) {
+  constexpr int MAXB = (FFT_POINTS / FFT_THREADS + R - 1) / R;
+  const int nb = N / R;
+  const int total = P * nb;
+  const int tstride = N / (Ns * R);
+  cplx<T> v[MAXB][R];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int b = threadIdx.x + i * FFT_THREADS;
+    if (b < total) {
+      const int p = b / nb, j = b - p * nb, jm = j % Ns;
+      const cplx<T>* src = lds + p * N + j;
+      v[i][0] = src[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[i][q] = cmul(src[q * nb], tw[q * jm * tstride]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int b = threadIdx.x + i * FFT_THREADS;
+    if (b < total) {
+      dft<R>(v[i]);
+      const int p = b / nb, j = b - p * nb, jm = j % Ns;
+      cplx<T>* dst = lds + p * N + (j - jm) * R + jm;
+#pragma unroll
+      for (int q = 0; q < R; ++q) dst[q * Ns] = v[i][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Forward (unnormalised, exp(-2 pi i kt/N)) FFT of P series in LDS.
+template <class T>
+__device__ void fft_lds(cplx<T>* lds, const FftPlan& plan, int P, const cplx<T>* __restrict__ tw) {
+  int Ns = 1;
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.rad[s];
+    switch (R) {
+      case 2: fft_pass<2>(lds, plan.N, P, Ns, tw); break;
+      case 3: fft_pass<3>(lds, plan.N, P, Ns, tw); break;
+      case 4: fft_pass<4>(lds, plan.N, P, Ns, tw); break;
+      case 5: fft_pass<5>(lds, plan.N, P, Ns, tw); break;
+      case 7: fft_pass<7>(lds, plan.N, P, Ns, tw); break;
+      default: fft_pass<8>(lds, plan.N, P, Ns, tw); break;
+    }
+    Ns *= R;
+  }
+}
+
+// ---- phases 1+2: pad (+round) + real FFT -------------------------------------
+
+template <class TC, class TO>
+__global__ __launch_bounds__(FFT_THREADS) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
+                                                               const cplx<TC>* __restrict__ tw,
+                                                               int P, int64_t npb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<TC>* lds = reinterpret_cast<cplx<TC>*>(smem_raw);
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t b = wg / npb, pb = wg - b * npb;
+  const int64_t s0 = pb * 2 * P;
+  const int N = plan.N, Nt = a.Nt, two_p = 2 * P;
+  const int tid = threadIdx.x;
+
+  // zero padding t = Nt .. N-1 (phase 1)
+  const int padlen = N - Nt;
+  for (int i = tid; i < P * padlen; i += FFT_THREADS) {
+    const int p = i / padlen, t = Nt + (i - p * padlen);
+    lds[p * N + t] = {(TC)0, (TC)0};
+  }
+  // load, rounded to the pad and FFT formats; series 2p -> real, 2p+1 -> imaginary
+  const double* xb = a.x + b * a.x_rhs_stride;
+  for (int i = tid; i < Nt * two_p; i += FFT_THREADS) {
+    const int t = i / two_p, j = i - t * two_p;
+    const int64_t s = s0 + j;
+    double v = (s < a.S) ? xb[(int64_t)t * a.x_row_stride + s] : 0.0;
+    v = round_to(round_to(v, a.r_pad), a.r_fft);
+    TC* comp = reinterpret_cast<TC*>(lds + (j >> 1) * N + t);
+    comp[j & 1] = (TC)v;
+  }
+  __syncthreads();
+
+  fft_lds(lds, plan, P, tw);
+
+  // separate the two real spectra: X = (Z_k + conj Z_{N-k}) / 2,
+  // Y = (Z_k - conj Z_{N-k}) / 2i; keep bins 0 .. N/2
+  const int K = N / 2 + 1;
+  TO* outb = reinterpret_cast<TO*>(a.out);
+  for (int i = tid; i < K * two_p; i += FFT_THREADS) {
+    const int k = i / two_p, j = i - k * two_p;
+    const int64_t s = s0 + j;
+    if (s >= a.S) continue;
+    const cplx<TC>* z = lds + (j >> 1) * N;
+    const cplx<TC> zk = z[k], zr = z[k == 0 ? 0 : N - k];
+    cplx<TC> X;
+    if ((j & 1) == 0) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
+    else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
+    X = round_to(round_to(X, a.r_fft), a.r_next);
+    const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + (s / a.ncol) * a.ld_row + s % a.ncol;
+    outb[2 * off] = (TO)X.x;
+    outb[2 * off + 1] = (TO)X.y;
+  }
+}
+
+// ---- phases 4+5: inverse real FFT + scale + unpad ---------------------------
+
+template <class TI, class TC>
+__global__ __launch_bounds__(FFT_THREADS) void irfft_unpad_kernel(IrfftArgs a, FftPlan plan,
+                                                                  const cplx<TC>* __restrict__ tw,
+                                                                  int P, int64_t npb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<TC>* lds = reinterpret_cast<cplx<TC>*>(smem_raw);
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t b = wg / npb, pb = wg - b * npb;
+  const int64_t s0 = pb * 2 * P;
+  const int N = plan.N, Nt = a.Nt, two_p = 2 * P, hN = N / 2;
+  const int tid = threadIdx.x;
+  const TI* inb = reinterpret_cast<const TI*>(a.in);
+
+  // Z = A + iB over the full length from the two half spectra (Hermitian
+  // extension; the imaginary parts of bins 0 and N/2 are dropped, as a real
+  // inverse transform does).  LDS receives conj(Z): the inverse transform is
+  // conj(FFT(conj Z)).
+  const int K = hN + 1;
+  for (int i = tid; i < K * P; i += FFT_THREADS) {
+    const int k = i / P, p = i - k * P;
+    const int64_t s = s0 + 2 * p;
+    const int64_t base = k * a.in_k_stride + b * a.in_rhs_stride;
+    cplx<TC> A = {(TC)0, (TC)0}, B = {(TC)0, (TC)0};
+    if (s < a.S) A = {(TC)inb[2 * (base + s)], (TC)inb[2 * (base + s) + 1]};
+    if (s + 1 < a.S) B = {(TC)inb[2 * (base + s + 1)], (TC)inb[2 * (base + s + 1) + 1]};
+    A = round_to(A, a.r_ifft);
+    B = round_to(B, a.r_ifft);
+    if (k == 0 || k == hN) {
+      A.y = (TC)0;
+      B.y = (TC)0;
+    }
+    lds[p * N + k] = {A.x - B.y, -(A.y + B.x)};
+    if (k > 0 && k < hN) lds[p * N + N - k] = {A.x + B.y, A.y - B.x};
+  }
+  __syncthreads();
+
+  fft_lds(lds, plan, P, tw);
+
+  const TC inv_n = (TC)(1.0 / (double)N);
+  double* yb = a.y + b * a.y_rhs_stride;
+  for (int i = tid; i < Nt * two_p; i += FFT_THREADS) {
+    const int t = i / two_p, j = i - t * two_p;
+    const int64_t s = s0 + j;
+    if (s >= a.S) continue;
+    const cplx<TC> z = lds[(j >> 1) * N + t];  // conj of N * (a_t + i b_t)
+    TC v = ((j & 1) == 0 ? z.x : -z.y) * inv_n;
+    v = round_to(v, a.r_ifft);
+    yb[(int64_t)t * a.y_row_stride + s] = round_to((double)v, a.r_unpad);
+  }
+}
+
+// ---- host launchers -----------------------------------------------------------
+
+static int pairs_per_wg(int N, int64_t S) {
+  int P = FFT_POINTS / N;
+  if (P < 1) P = 1;
+  const int64_t need = (S + 1) / 2;
+  if (need < P) P = (int)need;
+  return P;
+}
+
+template <class TC, class TO>
+static hipError_t rfft_go(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
+  const int P = pairs_per_wg(plan.N, a.S);
+  const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
+  const int64_t nwg = npb * a.nrhs;
+  if (nwg <= 0) return hipSuccess;
+  const size_t lds = (size_t)P * plan.N * sizeof(cplx<TC>);
+  hipLaunchKernelGGL((rfft_pad_kernel<TC, TO>), dim3((unsigned)nwg), dim3(FFT_THREADS), lds, st, a,
+                     plan, reinterpret_cast<const cplx<TC>*>(tw), P, npb);
+  return hipGetLastError();
+}
+
+hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan, const void* tw,
+                       hipStream_t st) {
+  if (tc64) return out64 ? rfft_go<double, double>(a, plan, tw, st) : rfft_go<double, float>(a, plan, tw, st);
+  return rfft_go<float, float>(a, plan, tw, st);
+}
+
+template <class TI, class TC>
+static hipError_t irfft_go(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
+  const int P = pairs_per_wg(plan.N, a.S);
+  const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
+  const int64_t nwg = npb * a.nrhs;
+  if (nwg <= 0) return hipSuccess;
+  const size_t lds = (size_t)P * plan.N * sizeof(cplx<TC>);
+  hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC>), dim3((unsigned)nwg), dim3(FFT_THREADS), lds, st,
+                     a, plan, reinterpret_cast<const cplx<TC>*>(tw), P, npb);
+  return hipGetLastError();
+}
+
+hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan, const void* tw,
+                        hipStream_t st) {
+  if (tc64) return in64 ? irfft_go<double, double>(a, plan, tw, st) : irfft_go<float, double>(a, plan, tw, st);
+  return irfft_go<float, float>(a, plan, tw, st);
+}
+
+}  // namespace ftm

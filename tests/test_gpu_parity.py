@@ -1,0 +1,281 @@
+"""Parity of the HIP path against the CPU oracle (run on an MI355X).
+
+Every product goes through the C ABI (``libftm.so`` via ``Operator``); the
+expected values come only from ``oracle/``.  Sizes span several tiles of
+every kernel and ragged tails (odd Nm, Nd not a multiple of the 8-row block,
+Nm not a multiple of the 8-column padding, L with radices 2, 3, 5, 7, 8).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import PAPER, Shape, config_inputs, make_F, make_d, make_m
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12  # relative L2, float64 path
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    return oracle.relative_l2(a, b)
+
+
+def _run(F, m=None, d=None, **kw):
+    import torch
+    from paper_2508_10202_amd import Operator
+    op = Operator(torch.from_numpy(F).cuda(), **kw)
+    out = {}
+    if m is not None:
+        out["d"] = op.matvec(torch.from_numpy(m).cuda()).cpu().numpy()
+    if d is not None:
+        out["m"] = op.rmatvec(torch.from_numpy(d).cuda()).cpu().numpy()
+    op.close()
+    return out
+
+
+def test_tiny_config_fp64(gpu):
+    """Nt=64, Nd=16, Nm=256, iid N(0,1): forward and adjoint vs the oracle."""
+    s, F, m, d = config_inputs("tiny")
+    _say("case tiny", s)
+    out = _run(F, m[0], d[0])
+    ref_d, ref_m = oracle.forward(F, m[0]), oracle.adjoint(F, d[0])
+    assert _rel(out["d"], ref_d) <= FP64_TOL
+    assert _rel(out["m"], ref_m) <= FP64_TOL
+    assert np.max(np.abs(out["d"] - ref_d)) <= FP64_TOL * np.max(np.abs(ref_d))
+    assert np.max(np.abs(out["m"] - ref_m)) <= FP64_TOL * np.max(np.abs(ref_m))
+    # adjoint identity on the GPU's own outputs
+    lhs, rhs = float(np.dot(out["d"].ravel(), d[0].ravel())), float(np.dot(m[0].ravel(), out["m"].ravel()))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+RAGGED = [
+    Shape(45, 13, 301, decay=30.0),   # L = 90 = 2*3*3*5, odd Nm, Nd not a multiple of 8
+    Shape(7, 3, 5, decay=None),       # L = 14 = 2*7
+    Shape(1, 1, 1, decay=None),       # L = 2, a single block
+    Shape(2048, 2, 9, decay=500.0),   # largest supported Nt, L = 4096
+    Shape(100, 37, 1000),             # L = 200, several column tiles
+    Shape(12, 9, 24, scale_by_sqrt_nm=False, decay=None),  # L = 24 = 8*3
+]
+
+
+@pytest.mark.parametrize("s", RAGGED, ids=lambda s: f"Nt{s.Nt}_Nd{s.Nd}_Nm{s.Nm}")
+def test_ragged_shapes_fp64(gpu, s):
+    _say("case ragged", s)
+    F, m, d = make_F(s, 11), make_m(s, 12)[0], make_d(s, 13)[0]
+    out = _run(F, m, d)
+    assert _rel(out["d"], oracle.forward(F, m)) <= FP64_TOL
+    assert _rel(out["m"], oracle.adjoint(F, d)) <= FP64_TOL
+
+
+def test_identity_and_delay_blocks_exact(gpu):
+    """F_0 = I gives d = m, F_2 = I a two-block delay (up to float64 rounding of the FFTs)."""
+    Nt, n = 30, 8
+    for lag in (0, 2):
+        F = np.zeros((Nt, n, n))
+        F[lag] = np.eye(n)
+        m = make_m(Shape(Nt, n, n), 21)[0]
+        out = _run(F, m, m)
+        want_f = np.zeros_like(m)
+        want_f[lag:] = m[:Nt - lag]
+        want_a = np.zeros_like(m)
+        want_a[:Nt - lag] = m[lag:]
+        assert np.max(np.abs(out["d"] - want_f)) <= 1e-14
+        assert np.max(np.abs(out["m"] - want_a)) <= 1e-14
+
+
+def test_spectrum_fp64_vs_oracle(gpu):
+    import torch
+    from paper_2508_10202_amd import Operator
+    for s in (Shape(64, 5, 33, scale_by_sqrt_nm=False, decay=None), Shape(45, 3, 17, decay=None),
+              Shape(7, 2, 3, decay=None)):
+        _say("case spectrum", s)
+        F = make_F(s, 31)
+        op = Operator(torch.from_numpy(F).cuda())
+        got = op.spectrum("d").cpu().numpy()
+        op.close()
+        ref = oracle.spectrum(F)
+        assert got.shape == ref.shape
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def _rne(x, p):
+    """Round float64 x to p significand bits, nearest-even (normal range only)."""
+    mant, e = np.frexp(x)
+    return np.ldexp(np.rint(np.ldexp(mant, p)), e - p)
+
+
+def test_spectrum_storage_formats(gpu):
+    """The FP32/FP16/BF16 copies are the float64 spectrum rounded to nearest even."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(50, 6, 40, scale_by_sqrt_nm=False, decay=None)
+    F = make_F(s, 41)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("d", "s", "h", "b"))
+    ref = op.spectrum("d").cpu().numpy()
+    got = {w: op.spectrum(w).cpu().numpy() for w in "shb"}
+    op.close()
+    for part in (np.real, np.imag):
+        r = part(ref)
+        assert np.array_equal(part(got["s"]), r.astype(np.float32).astype(np.float64))
+        assert np.array_equal(part(got["h"]), r.astype(np.float16).astype(np.float64))
+        assert np.array_equal(part(got["b"]), _rne(r, 8))
+
+
+def test_multi_rhs_matches_single_bitwise(gpu):
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(40, 10, 200)
+    F, M, D = make_F(s, 51), make_m(s, 52, nrhs=3), make_d(s, 53, nrhs=3)
+    op = Operator(torch.from_numpy(F).cuda(), max_rhs=4)
+    Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
+    batch_d, batch_m = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
+    for b in range(3):
+        assert np.array_equal(batch_d[b], op.matvec(Mt[b]).cpu().numpy())
+        assert np.array_equal(batch_m[b], op.rmatvec(Dt[b]).cpu().numpy())
+    op.close()
+    assert _rel(batch_d, oracle.forward(F, M)) <= FP64_TOL
+    assert _rel(batch_m, oracle.adjoint(F, D)) <= FP64_TOL
+
+
+def test_repeat_is_bitwise_deterministic(gpu):
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(64, 16, 256)
+    F, m = make_F(s, 61), make_m(s, 62)[0]
+    op = Operator(torch.from_numpy(F).cuda(), fwd="sssss", adj="dhhhd", spectra=("d",))
+    mt = torch.from_numpy(m).cuda()
+    dt = torch.from_numpy(make_d(s, 63)[0]).cuda()
+    a1, a2 = op.matvec(mt).cpu(), op.matvec(mt).cpu()
+    b1, b2 = op.rmatvec(dt).cpu(), op.rmatvec(dt).cpu()
+    op.close()
+    assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+def test_abi_errors_on_gpu(gpu):
+    import torch
+    from paper_2508_10202_amd import FtmError, Operator
+    s = Shape(16, 4, 8)
+    op = Operator(torch.from_numpy(make_F(s, 71)).cuda(), max_rhs=2)
+    m = torch.zeros((3, s.Nt, s.Nm), dtype=torch.float64, device="cuda")
+    with pytest.raises(FtmError) as ei:
+        op.matvec(m)                  # nrhs 3 > max_rhs 2
+    assert ei.value.status == 1
+    with pytest.raises(FtmError) as ei:
+        op.set_precision(fwd="ddsdd")  # FP32 spectrum not kept
+    assert ei.value.status == 2
+    buf = torch.zeros(s.Nt * max(s.Nm, s.Nd) * 2, dtype=torch.float64, device="cuda")
+    from paper_2508_10202_amd._lib import lib
+    rc = lib().ftm_matvec(op.handle, buf.data_ptr(), buf.data_ptr() + 8, 1, None)
+    assert rc == 1                    # input and output overlap
+    op.close()
+
+
+# --- mixed precision ---------------------------------------------------------------
+
+U = {"d": 2.0 ** -53, "s": 2.0 ** -24, "h": 2.0 ** -11, "b": 2.0 ** -8}
+
+
+def mp_bounds(prec: str, L: int, n: int):
+    """Tolerance window for one precision string, shaped after eq. (error):
+    pad/unpad rounding once, FFT/IFFT growing like log2 L, the product's
+    storage rounding of Fhat and of its input, and its accumulation error
+    (float32 accumulation: log2 n).  ``hi`` = 4x that budget; ``lo`` = the
+    largest unit roundoff present / 64, so a phase that silently skips its
+    rounding fails too."""
+    from paper_2508_10202_amd import Precision
+    p = Precision.parse(prec)
+    ch = prec.split("+")[0]
+    acc = U["d"] if p.accum == 0 else U["s"]
+    lg = math.log2(L)
+    budget = (U[ch[0]] + U[ch[1]] * lg + 2 * U[ch[2]] + acc * math.log2(max(n, 2))
+              + U[ch[3]] * lg + U[ch[4]] + U["d"] * lg)
+    lo = max(U[c] for c in ch) / 64 if ch != "ddddd" else 0.0
+    return lo, 4 * budget + 1e-14
+
+
+MP_CONFIGS = ["sdddd", "dsddd", "ddsdd", "ddsdd+a64", "dddsd", "dddds", "dssdd", "ddssd", "sssss",
+              "ddhdd", "ddbdd", "dhddd", "dbddd", "dddhd", "dddbd", "hdddd", "ddddb",
+              "dhhhd", "dbbbd", "hhhhh", "bbbbb", "shsbs"]
+
+
+@pytest.fixture(scope="module")
+def mp_case():
+    s = Shape(200, 24, 1000)
+    F, m, d = make_F(s, 81), make_m(s, 82)[0], make_d(s, 83)[0]
+    return s, F, m, d, oracle.forward(F, m), oracle.adjoint(F, d)
+
+
+@pytest.mark.parametrize("prec", MP_CONFIGS)
+def test_mixed_precision_within_tolerance(gpu, mp_case, prec):
+    s, F, m, d, ref_d, ref_m = mp_case
+    _say("case mixed", prec)
+    out = _run(F, m, d, fwd=prec, adj=prec)
+    e_f, e_a = _rel(out["d"], ref_d), _rel(out["m"], ref_m)
+    lo_f, hi_f = mp_bounds(prec, s.L, s.Nm)
+    lo_a, hi_a = mp_bounds(prec, s.L, s.Nd)
+    _say(f"  {prec}: fwd {e_f:.3e} in [{lo_f:.1e}, {hi_f:.1e}], adj {e_a:.3e} in [{lo_a:.1e}, {hi_a:.1e}]")
+    assert lo_f <= e_f <= hi_f
+    assert lo_a <= e_a <= hi_a
+
+
+# --- the paper's shape at full size -----------------------------------------------------
+
+@pytest.fixture(scope="module")
+def paper_case():
+    s, F, m, d = config_inputs("paper")
+    return s, F, m[0], d[0]
+
+
+def test_paper_shape_fp64_full_vectors(gpu, paper_case):
+    """Nt=1000, Nd=100, Nm=5000 in float64: whole outputs vs the oracle, plus
+    exactly rounded single entries."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s, F, m, d = paper_case
+    _say("case paper fp64")
+    op = Operator(torch.from_numpy(F).cuda())
+    got_d = op.matvec(torch.from_numpy(m).cuda()).cpu().numpy()
+    got_m = op.rmatvec(torch.from_numpy(d).cuda()).cpu().numpy()
+    op.close()
+    ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
+    e_f, e_a = _rel(got_d, ref_d), _rel(got_m, ref_m)
+    _say(f"  paper fp64 rel err fwd {e_f:.3e} adj {e_a:.3e}")
+    assert e_f <= FP64_TOL and e_a <= FP64_TOL
+    rng = np.random.default_rng(5)
+    ii, rr = rng.integers(0, s.Nt, 12), rng.integers(0, s.Nd, 12)
+    ii[0], rr[0] = s.Nt - 1, s.Nd - 1                  # the longest sum
+    ex = oracle.forward_entries(F, m, ii, rr)
+    assert _rel(got_d[ii, rr], ex) <= FP64_TOL
+    jj, cc = rng.integers(0, s.Nt, 12), rng.integers(0, s.Nm, 12)
+    jj[0], cc[0] = 0, s.Nm - 1
+    ea = oracle.adjoint_entries(F, d, jj, cc)
+    assert _rel(got_m[jj, cc], ea) <= FP64_TOL
+
+
+def test_paper_shape_mixed(gpu, paper_case):
+    """The paper's optimum (FFT(m) and the product in FP32) and the all-FP32
+    and half-storage configurations at the full shape."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s, F, m, d = paper_case
+    ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s", "h", "b"))
+    mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
+    for fwd, adj in (("dssdd", "ddssd"), ("sssss", "sssss"), ("ddsdd+a64", "ddsdd+a64"),
+                     ("dhhhd", "dhhhd"), ("dbbbd", "dbbbd")):
+        _say("case paper mixed", fwd, adj)
+        op.set_precision(fwd=fwd, adj=adj)
+        e_f = _rel(op.matvec(mt).cpu().numpy(), ref_d)
+        e_a = _rel(op.rmatvec(dt).cpu().numpy(), ref_m)
+        lo_f, hi_f = mp_bounds(fwd, s.L, s.Nm)
+        lo_a, hi_a = mp_bounds(adj, s.L, s.Nd)
+        _say(f"  {fwd}/{adj}: fwd {e_f:.3e} [{lo_f:.1e},{hi_f:.1e}] adj {e_a:.3e} [{lo_a:.1e},{hi_a:.1e}]")
+        assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
+    op.close()

@@ -1,0 +1,95 @@
+"""Host-only checks of the C ABI library: it loads, exports what the header
+declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ftm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(ftm_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2508_10202_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libftm.so is not built: run __graft_entry__.build()")
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("ftm_setup_operator", "ftm_matvec", "ftm_rmatvec", "ftm_destroy_operator"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    from paper_2508_10202_amd import _lib
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    assert L.ftm_status_string(0) == b"ok"
+    assert L.ftm_status_string(1) == b"invalid argument"
+    assert L.ftm_status_string(99) == b"unknown status"
+
+
+def _setup(L, out, F, Nt, Nd, Nm, fwd=None, adj=None, spectra=0, max_rhs=1):
+    return L.ftm_setup_operator(out, F, Nt, Nd, Nm, fwd, adj, spectra, max_rhs, None)
+
+
+def test_setup_rejects_bad_arguments_without_a_gpu(L):
+    from paper_2508_10202_amd._lib import ERR_INVALID, ERR_UNSUPPORTED, FtmPrecision
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    assert _setup(L, None, fake, 4, 2, 3) == ERR_INVALID
+    assert _setup(L, ctypes.byref(h), None, 4, 2, 3) == ERR_INVALID
+    assert _setup(L, ctypes.byref(h), fake, 0, 2, 3) == ERR_INVALID
+    assert _setup(L, ctypes.byref(h), fake, 4, 0, 3) == ERR_INVALID
+    assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, max_rhs=0) == ERR_INVALID
+    assert b"max_rhs" in L.ftm_last_error()
+    # 2*Nt = 22 has the prime factor 11
+    assert _setup(L, ctypes.byref(h), fake, 11, 2, 3) == ERR_UNSUPPORTED
+    assert _setup(L, ctypes.byref(h), fake, 4096, 2, 3) == ERR_UNSUPPORTED
+    assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, spectra=1 << 5) == ERR_INVALID
+    bad = FtmPrecision(0, 0, 0, 0, 0, 1)      # FP64 product with FP32 accumulation
+    assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, fwd=ctypes.byref(bad)) == ERR_INVALID
+    bad = FtmPrecision(0, 0, 2, 0, 0, 0)      # FP16 product with FP64 accumulation
+    assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, adj=ctypes.byref(bad)) == ERR_INVALID
+    bad = FtmPrecision(0, 7, 0, 0, 0, 0)
+    assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, fwd=ctypes.byref(bad)) == ERR_INVALID
+    assert h.value is None
+
+
+def test_calls_on_null_operator(L):
+    from paper_2508_10202_amd._lib import ERR_INVALID, OK
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ftm_matvec(None, fake, fake, 1, None) == ERR_INVALID
+    assert L.ftm_rmatvec(None, fake, fake, 1, None) == ERR_INVALID
+    assert L.ftm_set_precision(None, None, None) == ERR_INVALID
+    assert L.ftm_get_spectrum(None, 0, 0, 1, fake, None) == ERR_INVALID
+    assert L.ftm_operator_info(None, None, None, None, None, None) == ERR_INVALID
+    assert L.ftm_destroy_operator(None) == OK
+
+
+def test_precision_strings():
+    from paper_2508_10202_amd import BF16, F16, F32, F64, Precision
+    p = Precision.parse("dssdd")
+    assert (p.pad, p.fft, p.gemv, p.ifft, p.unpad, p.accum) == (F64, F32, F32, F64, F64, F32)
+    assert str(p) == "dssdd"
+    q = Precision.parse("dhbsd+a32")
+    assert (q.fft, q.gemv, q.ifft, q.accum) == (F16, BF16, F32, F32)
+    assert str(Precision.parse("ddsdd+a64")) == "ddsdd+a64"
+    assert Precision.parse("ddddd") == Precision()
+    for bad in ("dddd", "dxddd", "ddddd+a16"):
+        with pytest.raises(ValueError):
+            Precision.parse(bad)
