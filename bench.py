@@ -95,8 +95,16 @@ def main() -> int:
     ap.add_argument("--mixed", choices=["none", "default", "all"], default="default",
                     help="mixed-precision configurations to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the CPU oracle (no errors, no CPU baseline): for profiler runs")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="after the timed work, copy a buffer of this size 3 times (device to device) "
+                         "so HBM byte counters can be scaled against a plain copy of known size")
     ap.add_argument("--json-out", default=None, help="also write the full record here")
     args = ap.parse_args()
+    if args.no_oracle:
+        args.mixed = "none"
+        args.no_cpu_baseline = True
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the distributed "
@@ -161,10 +169,14 @@ def main() -> int:
 
     # CPU oracle: timed baseline and reference for the errors
     import oracle
+    if args.no_oracle:
+        ref_d, ref_m = got_d, got_m
     t2 = time.perf_counter()
-    ref_d = oracle.forward(F, m)
+    if not args.no_oracle:
+        ref_d = oracle.forward(F, m)
     t3 = time.perf_counter()
-    ref_m = oracle.adjoint(F, d)
+    if not args.no_oracle:
+        ref_m = oracle.adjoint(F, d)
     t4 = time.perf_counter()
     try:
         from threadpoolctl import threadpool_info
@@ -176,8 +188,10 @@ def main() -> int:
         cpu_baseline = {"value": 2.0 / (t4 - t2), "unit": "matvecs/s", "cores": int(cores), "kind": "oracle",
                         "sample": f"one forward ({t3 - t2:.2f}s) and one adjoint ({t4 - t3:.2f}s) float64 "
                                   "oracle matvec at Nt=1000, Nd=100, Nm=5000, whole vectors"}
-    rel = {"fwd": oracle.relative_l2(got_d, ref_d), "adj": oracle.relative_l2(got_m, ref_m)}
-    log(f"fp64 rel err fwd {rel['fwd']:.3e} adj {rel['adj']:.3e}; oracle {t4 - t2:.1f}s")
+    rel = None if args.no_oracle else {"fwd": oracle.relative_l2(got_d, ref_d),
+                                       "adj": oracle.relative_l2(got_m, ref_m)}
+    if rel:
+        log(f"fp64 rel err fwd {rel['fwd']:.3e} adj {rel['adj']:.3e}; oracle {t4 - t2:.1f}s")
 
     mixed = None
     if args.mixed != "none":
@@ -228,6 +242,15 @@ def main() -> int:
         "mixed": mixed,
     }
     op.close()
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * 2 ** 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = n * 8
+        log(f"copy calibration: 3 x {n * 8} bytes")
     if args.json_out:
         with open(args.json_out, "w") as fh:
             json.dump(rec, fh, indent=1)
