@@ -87,6 +87,160 @@ def traffic_record():
     return rec.get("bytes_per_launch")
 
 
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def multi_rhs_section(log):
+    """64 right-hand sides at Nt=512, Nd=128, Nm=4096: the per-frequency product
+    on the matrix cores (FP32 and BF16 storage, FP32 accumulation) against 64
+    separate float64 matvecs on the same GPU; four right-hand sides are checked
+    against the oracle."""
+    import torch
+
+    import oracle
+    from paper_2508_10202_amd import Operator
+    from workloads import MULTI_RHS_NRHS, config_inputs
+    s, F, M, D = config_inputs("multi_rhs", nrhs=MULTI_RHS_NRHS)
+    B = MULTI_RHS_NRHS
+    dev = torch.device("cuda:0")
+    op = Operator(torch.from_numpy(F).to(dev), spectra=("s", "b"), max_rhs=B)
+    Mt, Dt = torch.from_numpy(M).to(dev), torch.from_numpy(D).to(dev)
+    Yd = torch.empty((B, s.Nt, s.Nd), dtype=torch.float64, device=dev)
+    Ym = torch.empty((B, s.Nt, s.Nm), dtype=torch.float64, device=dev)
+    pick = [0, 21, 42, 63]
+    ref_d, ref_m = oracle.forward(F, M[pick]), oracle.adjoint(F, D[pick])
+    flops = 8.0 * s.K * s.Nd * s.Nm * B
+    out = {"workload": f"Nt={s.Nt} Nd={s.Nd} Nm={s.Nm}, {B} right-hand sides", "flops_per_product": flops}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        op.profile(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        p = op.profile_read()
+        op.profile(False)
+        return p
+
+    # baseline: 64 separate float64 matvecs per direction
+    op.set_precision(fwd="ddddd", adj="ddddd")
+    def sep():
+        for b in range(B):
+            op.matvec(Mt[b], out=Yd[b])
+            op.rmatvec(Dt[b], out=Ym[b])
+    p = timed(sep, reps=1)
+    base_f, base_a = sum(p["fwd"]) * B, sum(p["adj"]) * B
+    out["fp64_separate_ms"] = {"fwd": round(base_f, 3), "adj": round(base_a, 3)}
+    for prec, peak in (("ddsdd", PEAK_FP32_TFLOPS), ("dbbbd", PEAK_BF16_TFLOPS)):
+        op.set_precision(fwd=prec, adj=prec)
+        p = timed(lambda: (op.matvec(Mt, out=Yd), op.rmatvec(Dt, out=Ym)))
+        e_f = oracle.relative_l2(Yd[pick].cpu().numpy(), ref_d)
+        e_a = oracle.relative_l2(Ym[pick].cpu().numpy(), ref_m)
+        fbytes = 8 if prec[2] == "s" else 4
+        gemm_bytes = s.K * s.Nd * s.Nm * fbytes + s.K * B * (s.Nm + s.Nd) * 8
+        rec = {}
+        for name, kms, err, base in (("fwd", p["fwd"], e_f, base_f), ("adj", p["adj"], e_a, base_a)):
+            t = kms[1] * 1e-3
+            rec[name] = {"kernels_ms": [round(x, 4) for x in kms], "matvec_ms": round(sum(kms), 4),
+                         "gemm_tflops": round(flops / t / 1e12, 2), "mfma_frac": round(flops / t / 1e12 / peak, 4),
+                         "gemm_gbs": round(gemm_bytes / t / 1e9, 1), "rel_err": float(f"{err:.3e}"),
+                         "speedup_vs_fp64_separate": round(base / sum(kms), 2)}
+        out[prec] = rec
+        log(f"multi-rhs {prec}: " + json.dumps(rec))
+    op.close()
+    return out
+
+
+def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000.0):
+    """Poisson arrivals at `rate` req/s against 4 device-resident FP32
+    operators; each request is forward or adjoint (50/50) with 1..32 vectors,
+    operator uniform.  Workspace budget 4 GiB (it binds: a 32-vector request
+    on the largest operators needs 1.3-2.1 GB)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2508_10202_amd import Operator, Server
+    from workloads import SERVING_OPS, make_F, seed_for
+
+    dev = torch.device("cuda:0")
+    ops, Fs = [], []
+    for i, sh in enumerate(SERVING_OPS):
+        F = make_F(sh, seed_for(5, 10 + i))
+        Fs.append(F if i in (0, 1) else None)         # host copies kept for the sampled checks
+        ops.append(Operator(torch.from_numpy(F).to(dev), fwd="sssss", adj="sssss", spectra=("s",)))
+        del F
+    torch.cuda.synchronize()
+    # input pools: 2 per (operator, direction), 32 vectors each, iid N(0,1) (seeded)
+    g = torch.Generator(device=dev).manual_seed(seed_for(5, 3))
+    pools = {}
+    for i, op in enumerate(ops):
+        for adj in (0, 1):
+            n = op.Nd if adj else op.Nm
+            pools[i, adj] = [torch.randn((32, op.Nt, n), dtype=torch.float64, device=dev, generator=g)
+                             for _ in range(2)]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed_for(5, 4))
+    total = warmup + seconds
+    n_req = int(rate * total * 1.2) + 16
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    arrivals = arrivals[arrivals < total]
+    kinds = rng.integers(0, len(ops), len(arrivals))
+    dirs = rng.integers(0, 2, len(arrivals))
+    nrhs = rng.integers(1, 33, len(arrivals))
+    budget = 4 << 30
+    srv = Server(workspace_budget=budget, n_slots=4, max_batch_rhs=64)
+    tickets, keep = [], {}
+    sample = set(range(0, len(arrivals), max(1, len(arrivals) // 8)))
+    t0 = time.perf_counter()
+    for i, (ta, k, a, nr) in enumerate(zip(arrivals, kinds, dirs, nrhs)):
+        while time.perf_counter() - t0 < ta:
+            pass
+        x = pools[int(k), int(a)][i % 2][: int(nr)]
+        t, y = srv.submit(ops[int(k)], x, adjoint=bool(a))
+        tickets.append(t)
+        if i in sample and int(k) in (0, 1):
+            keep[i] = (t, y)
+        if i % 256 == 0:
+            srv.release_done()
+    for t in tickets:
+        srv.wait(t, timeout=120)
+    t_end = time.perf_counter() - t0
+    lat = srv.latencies(tickets[0], len(tickets))
+    st = srv.stats()
+    measured = arrivals >= warmup
+    lm = lat[measured] * 1e3
+    n_meas = int(measured.sum())
+    vec = int(nrhs[measured].sum())
+    out = {"workload": "4 FP32 operators (Nt,Nd,Nm) = " + ", ".join(f"({s.Nt},{s.Nd},{s.Nm})" for s in SERVING_OPS)
+                       + f"; Poisson {rate:g} req/s; forward/adjoint 50/50; 1-32 vectors uniform; {seconds:g} s "
+                       + f"measured after {warmup:g} s warm-up",
+           "requests": n_meas, "p50_ms": round(float(np.percentile(lm, 50)), 3),
+           "p99_ms": round(float(np.percentile(lm, 99)), 3), "mean_ms": round(float(lm.mean()), 3),
+           "throughput_req_s": round(n_meas / seconds, 1), "vectors_s": round(vec / seconds, 1),
+           "offered_req_s": rate, "wall_s": round(t_end, 2), "workspace_budget_bytes": budget, "stats": st}
+    # the same request alone on an idle server equals its result in the mix
+    diffs = []
+    for i, (t, y) in keep.items():
+        k, a, nr = int(kinds[i]), int(dirs[i]), int(nrhs[i])
+        x = pools[k, a][i % 2][:nr]
+        t2, y2 = srv.submit(ops[k], x, adjoint=bool(a))
+        srv.wait(t2, timeout=60)
+        xh = x.cpu().numpy()
+        ref = oracle.adjoint(Fs[k], xh) if a else oracle.forward(Fs[k], xh)
+        diffs.append({"request": i, "op": k, "adjoint": a, "nrhs": nr,
+                      "mix_vs_alone": float(f"{oracle.relative_l2(y.cpu().numpy(), y2.cpu().numpy()):.3e}"),
+                      "mix_vs_oracle": float(f"{oracle.relative_l2(y.cpu().numpy(), ref):.3e}")})
+    out["sampled_checks"] = diffs
+    srv.close()
+    for op in ops:
+        op.close()
+    log("serving: " + json.dumps({k: v for k, v in out.items() if k not in ("sampled_checks", "stats")}))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,11 +254,17 @@ def main() -> int:
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="after the timed work, copy a buffer of this size 3 times (device to device) "
                          "so HBM byte counters can be scaled against a plain copy of known size")
+    ap.add_argument("--no-multi-rhs", action="store_true",
+                    help="skip the 64-right-hand-side GEMM measurement (Nt=512, Nd=128, Nm=4096)")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="measured duration of the serving run (after a 1 s warm-up); 0 skips it")
     ap.add_argument("--json-out", default=None, help="also write the full record here")
     args = ap.parse_args()
     if args.no_oracle:
         args.mixed = "none"
         args.no_cpu_baseline = True
+        args.no_multi_rhs = True
+        args.serving_seconds = 0.0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the distributed "
@@ -223,6 +383,12 @@ def main() -> int:
                                                                    "speedup_vs_fp64": round(base / b["ms"], 3)}
         log("mixed best: " + json.dumps(mixed["best"]))
 
+    multi = None if args.no_multi_rhs else multi_rhs_section(log)
+    serving = None
+    if args.serving_seconds > 0:
+        op.close()
+        serving = serving_section(log, args.serving_seconds)
+
     achieved = gb_fwd
     roofline = {"bound": "hbm", "kernel": "gemv_fwd_kernel<s_f64,double,double,double> (phase 3, float64)",
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -239,7 +405,7 @@ def main() -> int:
         "hbm_gbs": {"fwd": round(matvec_bytes(s, 16) / (fwd_ms * 1e-3) / 1e9, 1),
                     "adj": round(matvec_bytes(s, 16) / (adj_ms * 1e-3) / 1e9, 1)},
         "kernels_ms": kms, "rel_err": rel, "roofline": roofline, "cpu_baseline": cpu_baseline,
-        "mixed": mixed,
+        "mixed": mixed, "multi_rhs": multi, "serving": serving,
     }
     op.close()
     if args.copy_calibration_gib > 0:

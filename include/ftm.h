@@ -108,6 +108,19 @@ ftm_status ftm_matvec(ftm_operator op, const double* m, double* d, int64_t nrhs,
  *   d device float64 [nrhs][Nt][Nd];  m device float64 [nrhs][Nt][Nm]. */
 ftm_status ftm_rmatvec(ftm_operator op, const double* d, double* m, int64_t nrhs, void* stream);
 
+/* How phase 3 treats nrhs > 1 right-hand sides:
+ *   FTM_RHS_AUTO  (default) matrix-core GEMM when the product's storage is
+ *                 FP32/FP16/BF16 with FP32 accumulation and nrhs >= the
+ *                 operator's crossover (see ftm_set_gemm_crossover), else one
+ *                 matrix-vector product per right-hand side
+ *   FTM_RHS_GEMV  always one matrix-vector product per right-hand side
+ *   FTM_RHS_GEMM  the GEMM whenever the configuration allows it */
+typedef enum ftm_rhs_mode { FTM_RHS_AUTO = 0, FTM_RHS_GEMV = 1, FTM_RHS_GEMM = 2 } ftm_rhs_mode;
+ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode);
+
+/* Smallest nrhs for which FTM_RHS_AUTO uses the GEMM (>= 2; default 2). */
+ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs);
+
 /* Copy bins k0 .. k0+nk-1 of the stored spectrum in storage precision
  * `which` (widened to float64) to out: device float64 [nk][Nd][Nm][2]
  * (real, imaginary).  Fhat_k = sum_{t<Nt} F_t exp(-2 pi i k t / L). */
@@ -135,6 +148,62 @@ ftm_status ftm_profile_read(ftm_operator op, double* ms, int64_t* counts, int32_
 /* Release everything the operator owns.  The caller must make sure no work
  * using it is still pending.  NULL is accepted and ignored. */
 ftm_status ftm_destroy_operator(ftm_operator op);
+
+/* ---- serving ------------------------------------------------------------
+ * Continuous batching of matvec requests against device-resident operators
+ * (one GPU).  A worker thread owns n_slots HIP streams and one workspace
+ * arena of workspace_budget bytes allocated at creation.  Whenever a slot is
+ * free it admits the oldest queued request together with every later queued
+ * request for the same operator and direction, up to max_batch_rhs
+ * right-hand sides, as one multi-right-hand-side matvec -- provided the
+ * batch's workspace fits in the unused part of the budget; otherwise the
+ * queue head waits (first in, first out) until running batches release
+ * workspace.  Batches on different slots overlap on the device.  Requests
+ * that arrive while others run are admitted as slots and workspace free up.
+ * Results are the same, within the precision configuration's tolerance, as
+ * a lone ftm_matvec/ftm_rmatvec of the same input (bitwise when the product
+ * takes the same path; see ftm_set_rhs_mode).
+ * The operators' precision configuration is read when a batch launches. */
+typedef struct ftm_server_s* ftm_server;
+
+typedef struct ftm_server_stats {
+  uint64_t submitted, completed, failed;
+  uint64_t batches;             /* launched batches */
+  uint64_t rhs_launched;        /* right-hand sides over all batches */
+  uint64_t coalesced_requests;  /* requests that shared a batch with others */
+  uint64_t budget_waits;        /* times the queue head had to wait for workspace */
+  int64_t max_inflight_requests, queued_requests;
+  size_t peak_workspace_bytes, workspace_in_use_bytes;
+} ftm_server_stats;
+
+/* workspace_budget >= 4 KiB, 1 <= n_slots <= 16, 1 <= max_batch_rhs <= 4096.
+ * Uses the current HIP device. */
+ftm_status ftm_server_create(ftm_server* out, size_t workspace_budget, int32_t n_slots, int64_t max_batch_rhs);
+
+/* Queue one request: adjoint = 0 computes y = F x (x [nrhs][Nt][Nm], y
+ * [nrhs][Nt][Nd]), adjoint != 0 computes y = F^T x (x [nrhs][Nt][Nd], y
+ * [nrhs][Nt][Nm]); device float64.  ready_event (a hipEvent_t, may be NULL)
+ * is waited for on the device before x is read: record it on the stream that
+ * produced x.  The caller keeps x, y and the event alive, and x and y
+ * untouched, until the ticket completes.  FTM_ERR_BUDGET: the request alone
+ * needs more workspace than the whole budget (it would never run). */
+ftm_status ftm_server_submit(ftm_server s, ftm_operator op, int32_t adjoint, const double* x, double* y,
+                             int64_t nrhs, void* ready_event, uint64_t* ticket);
+
+/* done = 1 once the request's output is written and visible to the device;
+ * latency_s (may be NULL) = completion time - submit time, seconds. */
+ftm_status ftm_server_poll(ftm_server s, uint64_t ticket, int32_t* done, double* latency_s);
+
+/* Block until the ticket completes (timeout_s <= 0: no limit). */
+ftm_status ftm_server_wait(ftm_server s, uint64_t ticket, double* latency_s, double timeout_s);
+
+/* Latencies of tickets first_ticket .. first_ticket+n-1 (NaN while pending). */
+ftm_status ftm_server_latencies(ftm_server s, uint64_t first_ticket, int64_t n, double* out);
+
+ftm_status ftm_server_get_stats(ftm_server s, ftm_server_stats* out);
+
+/* Drain every queued and running request, then release the server. */
+ftm_status ftm_server_destroy(ftm_server s);
 
 const char* ftm_status_string(ftm_status s);
 const char* ftm_last_error(void);

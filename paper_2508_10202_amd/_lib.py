@@ -17,10 +17,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libftm.so")
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_BUDGET, ERR_HIP, ERR_STATE = range(7)
 # ftm_dtype
 F64, F32, F16, BF16 = range(4)
+# ftm_rhs_mode
+RHS_AUTO, RHS_GEMV, RHS_GEMM = range(3)
 
 # Every symbol include/ftm.h declares.
 EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
            "ftm_get_spectrum", "ftm_operator_info", "ftm_profile_enable", "ftm_profile_read",
+           "ftm_set_rhs_mode", "ftm_set_gemm_crossover",
+           "ftm_server_create", "ftm_server_submit", "ftm_server_poll", "ftm_server_wait",
+           "ftm_server_latencies", "ftm_server_get_stats", "ftm_server_destroy",
            "ftm_destroy_operator",
            "ftm_status_string", "ftm_last_error")
 
@@ -28,6 +33,14 @@ EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec
 class FtmPrecision(ctypes.Structure):
     _fields_ = [("pad", ctypes.c_int32), ("fft", ctypes.c_int32), ("gemv", ctypes.c_int32),
                 ("ifft", ctypes.c_int32), ("unpad", ctypes.c_int32), ("accum", ctypes.c_int32)]
+
+
+class FtmServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("rhs_launched", ctypes.c_uint64),
+                ("coalesced_requests", ctypes.c_uint64), ("budget_waits", ctypes.c_uint64),
+                ("max_inflight_requests", ctypes.c_int64), ("queued_requests", ctypes.c_int64),
+                ("peak_workspace_bytes", ctypes.c_size_t), ("workspace_in_use_bytes", ctypes.c_size_t)]
 
 
 class FtmError(RuntimeError):
@@ -59,8 +72,17 @@ def lib() -> ctypes.CDLL:
         "ftm_operator_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                               ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],
         "ftm_profile_enable": [vp, i32],
+        "ftm_set_rhs_mode": [vp, i32],
+        "ftm_set_gemm_crossover": [vp, i64],
         "ftm_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32],
         "ftm_destroy_operator": [vp],
+        "ftm_server_create": [ctypes.POINTER(vp), ctypes.c_size_t, i32, i64],
+        "ftm_server_submit": [vp, vp, i32, vp, vp, i64, vp, ctypes.POINTER(ctypes.c_uint64)],
+        "ftm_server_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+        "ftm_server_wait": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), ctypes.c_double],
+        "ftm_server_latencies": [vp, ctypes.c_uint64, i64, ctypes.POINTER(ctypes.c_double)],
+        "ftm_server_get_stats": [vp, ctypes.POINTER(FtmServerStats)],
+        "ftm_server_destroy": [vp],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)

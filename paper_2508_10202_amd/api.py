@@ -167,6 +167,15 @@ class Operator:
                   "ftm_get_spectrum")
         return torch.view_as_complex(out)
 
+    def set_rhs_mode(self, mode: str) -> None:
+        """Phase 3 for several right-hand sides: "auto", "gemv" (one product per
+        vector) or "gemm" (matrix cores whenever the configuration allows)."""
+        code = {"auto": _lib.RHS_AUTO, "gemv": _lib.RHS_GEMV, "gemm": _lib.RHS_GEMM}[mode]
+        check(lib().ftm_set_rhs_mode(self.handle, code), "ftm_set_rhs_mode")
+
+    def set_gemm_crossover(self, min_rhs: int) -> None:
+        check(lib().ftm_set_gemm_crossover(self.handle, int(min_rhs)), "ftm_set_gemm_crossover")
+
     def profile(self, enable: bool = True) -> None:
         """Record HIP events around each kernel of every following call."""
         check(lib().ftm_profile_enable(self.handle, 1 if enable else 0), "ftm_profile_enable")
@@ -187,6 +196,91 @@ class Operator:
             torch.cuda.synchronize(self.device)
             lib().ftm_destroy_operator(self._h.value)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Continuous-batching request loop over device-resident operators.
+
+    ``submit`` returns at once with a ticket; the library's worker thread
+    admits requests by workspace budget, coalesces queued requests for the
+    same operator and direction into one multi-right-hand-side matvec, and
+    runs batches of different operators concurrently on ``n_slots`` streams.
+    """
+
+    def __init__(self, workspace_budget: int, n_slots: int = 4, max_batch_rhs: int = 64):
+        h = ctypes.c_void_p()
+        check(lib().ftm_server_create(ctypes.byref(h), int(workspace_budget), int(n_slots), int(max_batch_rhs)),
+              "ftm_server_create")
+        self._h = h
+        self.max_batch_rhs = int(max_batch_rhs)
+        self._live = {}  # ticket -> (x, y, event): kept alive until completion
+
+    def submit(self, op: Operator, x: torch.Tensor, adjoint: bool = False, out=None):
+        """Queue ``F x`` (or ``F^T x``); returns ``(ticket, y)``.  ``y`` is
+        written when the ticket completes.  ``x`` may still be in production on
+        the current stream: an event recorded there is waited for on the device."""
+        n_in, n_out = (op.Nd, op.Nm) if adjoint else (op.Nm, op.Nd)
+        x = _dev_f64(x, "x")
+        xb = x.unsqueeze(0) if x.dim() == 2 else x
+        if xb.dim() != 3 or tuple(xb.shape[1:]) != (op.Nt, n_in):
+            raise ValueError(f"input must be [nrhs,] {op.Nt} x {n_in}")
+        nrhs = xb.shape[0]
+        y = out if out is not None else torch.empty((nrhs, op.Nt, n_out), dtype=torch.float64, device=x.device)
+        ev = torch.cuda.Event()
+        ev.record()
+        t = ctypes.c_uint64()
+        check(lib().ftm_server_submit(self._h, op.handle, 1 if adjoint else 0, xb.data_ptr(), y.data_ptr(), nrhs,
+                                      ctypes.c_void_p(ev.cuda_event), ctypes.byref(t)), "ftm_server_submit")
+        self._live[t.value] = (xb, y, ev)
+        return t.value, y
+
+    def poll(self, ticket: int):
+        done, lat = ctypes.c_int32(), ctypes.c_double()
+        check(lib().ftm_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(lat)), "ftm_server_poll")
+        if done.value:
+            self._live.pop(ticket, None)
+        return bool(done.value), lat.value
+
+    def wait(self, ticket: int, timeout: float = 0.0) -> float:
+        lat = ctypes.c_double()
+        check(lib().ftm_server_wait(self._h, ticket, ctypes.byref(lat), float(timeout)), "ftm_server_wait")
+        self._live.pop(ticket, None)
+        return lat.value
+
+    def latencies(self, first: int, n: int):
+        import numpy as np
+        out = np.empty(n, dtype=np.float64)
+        check(lib().ftm_server_latencies(self._h, first, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              "ftm_server_latencies")
+        return out
+
+    def release_done(self) -> None:
+        """Drop references to tensors of completed requests."""
+        for t in list(self._live):
+            self.poll(t)
+
+    def stats(self) -> dict:
+        st = _lib.FtmServerStats()
+        check(lib().ftm_server_get_stats(self._h, ctypes.byref(st)), "ftm_server_get_stats")
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().ftm_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
 
     def __del__(self):
         try:

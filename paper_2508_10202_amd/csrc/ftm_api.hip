@@ -14,12 +14,17 @@
 #include "ftm.h"
 #include "ftm_device.h"
 #include "ftm_kernels.h"
+#include "ftm_runtime.h"
 
 using namespace ftm;
+using ftm_rt::DevBuf;
+using ftm_rt::DeviceGuard;
+using ftm_rt::fail;
+using ftm_rt::fail_hip;
 
-namespace {
+namespace ftm_rt {
 
-thread_local std::string g_last_error;
+static thread_local std::string g_last_error;
 
 ftm_status fail(ftm_status s, const std::string& msg) {
   g_last_error = msg;
@@ -30,11 +35,18 @@ ftm_status fail_hip(const char* what, hipError_t e) {
   return fail(FTM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define FTM_HIP(expr)                                  \
-  do {                                                 \
-    hipError_t e_ = (expr);                            \
-    if (e_ != hipSuccess) return fail_hip(#expr, e_);  \
-  } while (0)
+Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs) {
+  Workspace w;
+  char* p = reinterpret_cast<char*>(base);
+  w.mhat = p;
+  const size_t m_bytes = ((size_t)op->K * nrhs * op->ldm * 16 + 255) / 256 * 256;
+  w.dhat = p + m_bytes;
+  return w;
+}
+
+}  // namespace ftm_rt
+
+namespace {
 
 size_t dtype_bytes(int dt) {  // bytes of one complex number in storage format dt
   switch (dt) {
@@ -80,39 +92,7 @@ bool make_plan(int N, FftPlan* plan) {
   return true;
 }
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t n = 0;
-};
-
 }  // namespace
-
-struct ftm_operator_s {
-  int64_t Nt = 0, Nd = 0, Nm = 0, L = 0, K = 0;
-  int ldm = 0, ldd = 0;  // padded column counts of spectra and workspaces
-  int device = 0;
-  int64_t max_rhs = 1;
-  FftPlan plan{};
-  DevBuf tw64, tw32;       // exp(-2 pi i e / L), e = 0 .. L-1
-  DevBuf spec[4];          // Fhat[K][Nd][ldm] per storage format
-  DevBuf mhat, dhat;       // [K][max_rhs][ldm], [K][max_rhs][ldd] complex (float64-sized)
-  ftm_precision fwd = kAllF64, adj = kAllF64;
-
-  // instrumentation: events around the three kernels of each recorded call
-  bool profiling = false;
-  struct Rec {
-    int dir;
-    hipEvent_t ev[4];
-  };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> event_pool;
-
-  size_t bytes() const {
-    size_t b = tw64.n + tw32.n + mhat.n + dhat.n;
-    for (const auto& s : spec) b += s.n;
-    return b;
-  }
-};
 
 namespace {
 
@@ -146,22 +126,6 @@ void release(ftm_operator op) {
   dev_free(&op->mhat);
   dev_free(&op->dhat);
 }
-
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&old_) == hipSuccess && old_ != dev) {
-      if (hipSetDevice(dev) == hipSuccess) switched_ = true;
-    }
-  }
-  ~DeviceGuard() {
-    if (switched_) (void)hipSetDevice(old_);
-  }
-
- private:
-  int old_ = 0;
-  bool switched_ = false;
-};
 
 // Twiddle tables exp(-2 pi i e / L), evaluated in long double and rounded once.
 ftm_status upload_twiddles(ftm_operator op, hipStream_t st) {
@@ -228,10 +192,14 @@ struct Profiler {
   }
 };
 
+uint32_t needed_mask(const ftm_precision& f, const ftm_precision& a) { return (1u << f.gemv) | (1u << a.gemv); }
+
+}  // namespace
+
 // One direction of the matvec: x (float64, [nrhs][Nt][Sx]) -> y (float64,
 // [nrhs][Nt][Sy]).  adjoint selects Fhat^H in phase 3.
-ftm_status run_matvec(ftm_operator op, bool adjoint, const double* x, double* y, int64_t nrhs,
-                      hipStream_t st) {
+ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io, int64_t nrhs,
+                              const Workspace& ws, hipStream_t st) {
   const ftm_precision& p = adjoint ? op->adj : op->fwd;
   const void* F = op->spec[p.gemv].p;
   if (!F) return fail(FTM_ERR_STATE, "spectrum for the configured phase-3 precision is missing");
@@ -244,11 +212,13 @@ ftm_status run_matvec(ftm_operator op, bool adjoint, const double* x, double* y,
   const bool y_hat64 = p.gemv == DT_F64 && p.ifft == DT_F64;
   const int64_t Sx = adjoint ? op->Nd : op->Nm, Sy = adjoint ? op->Nm : op->Nd;
   const int ldx = adjoint ? op->ldd : op->ldm, ldy = adjoint ? op->ldm : op->ldd;
-  void* xhat = adjoint ? op->dhat.p : op->mhat.p;
-  void* yhat = adjoint ? op->mhat.p : op->dhat.p;
+  void* xhat = adjoint ? ws.dhat : ws.mhat;
+  void* yhat = adjoint ? ws.mhat : ws.dhat;
 
   RfftArgs ra{};
-  ra.x = x;
+  ra.x = io.x;
+  ra.xptr = io.xptr;
+  ra.pad_to = ldx;
   ra.x_rhs_stride = op->Nt * Sx;
   ra.x_row_stride = Sx;
   ra.S = Sx;
@@ -285,8 +255,18 @@ ftm_status run_matvec(ftm_operator op, bool adjoint, const double* x, double* y,
   ga.r_next = p.ifft;
   const bool acc64 = p.accum == DT_F64;
   prof.mark(1);
-  if (adjoint) FTM_HIP(launch_gemv_adj(p.gemv, acc64, x_hat64, y_hat64, ga, st));
-  else FTM_HIP(launch_gemv_fwd(p.gemv, acc64, x_hat64, y_hat64, ga, st));
+  // many right-hand sides: one pass of the spectrum through the matrix cores
+  const bool gemm_ok = p.gemv != DT_F64 && !acc64 && nrhs >= 2;
+  const bool use_gemm = gemm_ok && (op->rhs_mode == FTM_RHS_GEMM ||
+                                    (op->rhs_mode == FTM_RHS_AUTO && nrhs >= op->gemm_min_rhs));
+  if (use_gemm) {
+    if (adjoint) FTM_HIP(launch_gemm_adj(p.gemv, ga, st));
+    else FTM_HIP(launch_gemm_fwd(p.gemv, ga, st));
+  } else if (adjoint) {
+    FTM_HIP(launch_gemv_adj(p.gemv, acc64, x_hat64, y_hat64, ga, st));
+  } else {
+    FTM_HIP(launch_gemv_fwd(p.gemv, acc64, x_hat64, y_hat64, ga, st));
+  }
 
   IrfftArgs ia{};
   ia.in = yhat;
@@ -295,7 +275,8 @@ ftm_status run_matvec(ftm_operator op, bool adjoint, const double* x, double* y,
   ia.S = Sy;
   ia.Nt = (int)op->Nt;
   ia.nrhs = (int)nrhs;
-  ia.y = y;
+  ia.y = io.y;
+  ia.yptr = io.yptr;
   ia.y_rhs_stride = op->Nt * Sy;
   ia.y_row_stride = Sy;
   ia.r_ifft = p.ifft;
@@ -306,10 +287,6 @@ ftm_status run_matvec(ftm_operator op, bool adjoint, const double* x, double* y,
   prof.mark(3);
   return FTM_OK;
 }
-
-uint32_t needed_mask(const ftm_precision& f, const ftm_precision& a) { return (1u << f.gemv) | (1u << a.gemv); }
-
-}  // namespace
 
 extern "C" {
 
@@ -326,7 +303,7 @@ const char* ftm_status_string(ftm_status s) {
   return "unknown status";
 }
 
-const char* ftm_last_error(void) { return g_last_error.c_str(); }
+const char* ftm_last_error(void) { return ftm_rt::g_last_error.c_str(); }
 
 ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd, int64_t Nm,
                               const ftm_precision* fwd, const ftm_precision* adj, uint32_t spectra,
@@ -390,6 +367,7 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     ra.ncol = Nm;
     ra.ld_row = op->ldm;
     ra.r_pad = ra.r_fft = ra.r_next = DT_F64;
+    ra.pad_to = 0;  // the spectrum's padding is cleared above
     e = launch_rfft(true, true, ra, op->plan, op->tw64.p, st);
     if (e != hipSuccess) return bail(fail_hip("setup transform", e));
 
@@ -442,7 +420,13 @@ static ftm_status matvec_common(ftm_operator op, bool adjoint, const double* x, 
     const char* yb = reinterpret_cast<const char*>(y);
     if (xb < yb + ny * 8 && yb < xb + nx * 8) return fail(FTM_ERR_INVALID, "input and output overlap");
     DeviceGuard g(op->device);
-    return run_matvec(op, adjoint, x, y, nrhs, reinterpret_cast<hipStream_t>(stream));
+    ftm_rt::MatvecIO io;
+    io.x = x;
+    io.y = y;
+    ftm_rt::Workspace ws;
+    ws.mhat = op->mhat.p;
+    ws.dhat = op->dhat.p;
+    return ftm_rt::run_matvec(op, adjoint, io, nrhs, ws, reinterpret_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(FTM_ERR_INVALID, "unexpected exception in matvec");
   }
@@ -477,6 +461,20 @@ ftm_status ftm_operator_info(ftm_operator op, int64_t* Nt, int64_t* Nd, int64_t*
   if (Nm) *Nm = op->Nm;
   if (L) *L = op->L;
   if (device_bytes) *device_bytes = op->bytes();
+  return FTM_OK;
+}
+
+ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (mode < FTM_RHS_AUTO || mode > FTM_RHS_GEMM) return fail(FTM_ERR_INVALID, "unknown rhs mode");
+  op->rhs_mode = mode;
+  return FTM_OK;
+}
+
+ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (min_rhs < 2) return fail(FTM_ERR_INVALID, "the crossover is at least 2 right-hand sides");
+  op->gemm_min_rhs = min_rhs;
   return FTM_OK;
 }
 

@@ -7,6 +7,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef FTM_STREAM_NT
+#define FTM_STREAM_NT 1
+#endif
+
 namespace ftm {
 
 enum : int { DT_F64 = 0, DT_F32 = 1, DT_F16 = 2, DT_BF16 = 3 };
@@ -148,6 +152,20 @@ struct Chunk<s_bf16, TA> {
       out[i] = {(TA)__uint_as_float(w[i] << 16), (TA)__uint_as_float(w[i] & 0xffff0000u)};
   }
 };
+
+// ---------------------------------------------------------------------------
+// 16-byte load of data that is read exactly once (the stored spectrum): a
+// non-temporal load keeps it from displacing reused data in the caches and
+// streams measurably faster than a plain load on gfx950.
+typedef unsigned ftm_v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_stream(const void* p) {
+#if FTM_STREAM_NT
+  const ftm_v4u t = __builtin_nontemporal_load(reinterpret_cast<const ftm_v4u*>(p));
+  return make_uint4(t.x, t.y, t.z, t.w);
+#else
+  return *reinterpret_cast<const uint4*>(p);
+#endif
+}
 
 // ---------------------------------------------------------------------------
 // Workgroups are handed to the 8 XCDs round robin (workgroup i runs on XCD

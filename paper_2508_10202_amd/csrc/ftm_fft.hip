@@ -118,17 +118,17 @@ __device__ __forceinline__ void dft(cplx<T>* a) {
 // One Stockham pass of radix R over P series of length N held in LDS.
 // Ns is the product of the radices of the earlier passes.  All reads of the
 // pass complete (barrier) before any write, so the pass works in place.
-template <int R, class T>
+template <int R, int TH, int PTS, class T>
 __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
                                          const cplx<T>* __restrict__ tw) {
-  constexpr int MAXB = (FFT_POINTS / FFT_THREADS + R - 1) / R;
+  constexpr int MAXB = (PTS / TH + R - 1) / R;  // butterflies per thread
   const int nb = N / R;
   const int total = P * nb;
   const int tstride = N / (Ns * R);
   cplx<T> v[MAXB][R];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = threadIdx.x + i * FFT_THREADS;
+    const int b = threadIdx.x + i * TH;
     if (b < total) {
       const int p = b / nb, j = b - p * nb, jm = j % Ns;
       const cplx<T>* src = lds + p * N + j;
@@ -140,7 +140,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = threadIdx.x + i * FFT_THREADS;
+    const int b = threadIdx.x + i * TH;
     if (b < total) {
       dft<R>(v[i]);
       const int p = b / nb, j = b - p * nb, jm = j % Ns;
@@ -152,19 +152,23 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
   __syncthreads();
 }
 
-// Forward (unnormalised, exp(-2 pi i kt/N)) FFT of P series in LDS.
-template <class T>
+// Forward (unnormalised, exp(-2 pi i kt/N)) FFT of P series in LDS.  Plans
+// with a radix-7 pass use the R7 instantiation; the others do not carry its
+// register cost.
+template <class T, bool R7, int TH, int PTS>
 __device__ void fft_lds(cplx<T>* lds, const FftPlan& plan, int P, const cplx<T>* __restrict__ tw) {
   int Ns = 1;
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.rad[s];
     switch (R) {
-      case 2: fft_pass<2>(lds, plan.N, P, Ns, tw); break;
-      case 3: fft_pass<3>(lds, plan.N, P, Ns, tw); break;
-      case 4: fft_pass<4>(lds, plan.N, P, Ns, tw); break;
-      case 5: fft_pass<5>(lds, plan.N, P, Ns, tw); break;
-      case 7: fft_pass<7>(lds, plan.N, P, Ns, tw); break;
-      default: fft_pass<8>(lds, plan.N, P, Ns, tw); break;
+      case 2: fft_pass<2, TH, PTS>(lds, plan.N, P, Ns, tw); break;
+      case 3: fft_pass<3, TH, PTS>(lds, plan.N, P, Ns, tw); break;
+      case 4: fft_pass<4, TH, PTS>(lds, plan.N, P, Ns, tw); break;
+      case 5: fft_pass<5, TH, PTS>(lds, plan.N, P, Ns, tw); break;
+      case 7:
+        if constexpr (R7) fft_pass<7, TH, PTS>(lds, plan.N, P, Ns, tw);
+        break;
+      default: fft_pass<8, TH, PTS>(lds, plan.N, P, Ns, tw); break;
     }
     Ns *= R;
   }
@@ -172,8 +176,12 @@ __device__ void fft_lds(cplx<T>* lds, const FftPlan& plan, int P, const cplx<T>*
 
 // ---- phases 1+2: pad (+round) + real FFT -------------------------------------
 
-template <class TC, class TO>
-__global__ __launch_bounds__(FFT_THREADS) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
+// Loads per thread issued together before any is consumed (memory-level
+// parallelism for the strided time-series reads).
+constexpr int FFT_LOAD_BATCH = 4;
+
+template <class TC, class TO, bool R7, int TH, int PTS>
+__global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
                                                                const cplx<TC>* __restrict__ tw,
                                                                int P, int64_t npb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -186,29 +194,41 @@ __global__ __launch_bounds__(FFT_THREADS) void rfft_pad_kernel(RfftArgs a, FftPl
 
   // zero padding t = Nt .. N-1 (phase 1)
   const int padlen = N - Nt;
-  for (int i = tid; i < P * padlen; i += FFT_THREADS) {
+  for (int i = tid; i < P * padlen; i += TH) {
     const int p = i / padlen, t = Nt + (i - p * padlen);
     lds[p * N + t] = {(TC)0, (TC)0};
   }
   // load, rounded to the pad and FFT formats; series 2p -> real, 2p+1 -> imaginary
-  const double* xb = a.x + b * a.x_rhs_stride;
-  for (int i = tid; i < Nt * two_p; i += FFT_THREADS) {
-    const int t = i / two_p, j = i - t * two_p;
-    const int64_t s = s0 + j;
-    double v = (s < a.S) ? xb[(int64_t)t * a.x_row_stride + s] : 0.0;
-    v = round_to(round_to(v, a.r_pad), a.r_fft);
-    TC* comp = reinterpret_cast<TC*>(lds + (j >> 1) * N + t);
-    comp[j & 1] = (TC)v;
+  const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
+  const int nload = Nt * two_p;
+  for (int base = tid; base < nload; base += FFT_LOAD_BATCH * TH) {
+    double v[FFT_LOAD_BATCH];
+#pragma unroll
+    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
+      const int i = base + u * TH;
+      const int t = i / two_p, j = i - t * two_p;
+      const int64_t s = s0 + j;
+      v[u] = (i < nload && s < a.S) ? xb[(int64_t)t * a.x_row_stride + s] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
+      const int i = base + u * TH;
+      if (i < nload) {
+        const int t = i / two_p, j = i - t * two_p;
+        TC* comp = reinterpret_cast<TC*>(lds + (j >> 1) * N + t);
+        comp[j & 1] = (TC)round_to(round_to(v[u], a.r_pad), a.r_fft);
+      }
+    }
   }
   __syncthreads();
 
-  fft_lds(lds, plan, P, tw);
+  fft_lds<TC, R7, TH, PTS>(lds, plan, P, tw);
 
   // separate the two real spectra: X = (Z_k + conj Z_{N-k}) / 2,
   // Y = (Z_k - conj Z_{N-k}) / 2i; keep bins 0 .. N/2
   const int K = N / 2 + 1;
   TO* outb = reinterpret_cast<TO*>(a.out);
-  for (int i = tid; i < K * two_p; i += FFT_THREADS) {
+  for (int i = tid; i < K * two_p; i += TH) {
     const int k = i / two_p, j = i - k * two_p;
     const int64_t s = s0 + j;
     if (s >= a.S) continue;
@@ -222,12 +242,23 @@ __global__ __launch_bounds__(FFT_THREADS) void rfft_pad_kernel(RfftArgs a, FftPl
     outb[2 * off] = (TO)X.x;
     outb[2 * off + 1] = (TO)X.y;
   }
+  // the last pair block of a right-hand side also clears the padding columns
+  // (the products read them, multiplied by the spectrum's zero padding)
+  if (pb == npb - 1 && a.pad_to > a.S) {
+    const int npad = (int)(a.pad_to - a.S);
+    for (int i = tid; i < K * npad; i += TH) {
+      const int k = i / npad;
+      const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + a.S + (i - k * npad);
+      outb[2 * off] = (TO)0;
+      outb[2 * off + 1] = (TO)0;
+    }
+  }
 }
 
 // ---- phases 4+5: inverse real FFT + scale + unpad ---------------------------
 
-template <class TI, class TC>
-__global__ __launch_bounds__(FFT_THREADS) void irfft_unpad_kernel(IrfftArgs a, FftPlan plan,
+template <class TI, class TC, bool R7, int TH, int PTS>
+__global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan plan,
                                                                   const cplx<TC>* __restrict__ tw,
                                                                   int P, int64_t npb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -244,29 +275,41 @@ __global__ __launch_bounds__(FFT_THREADS) void irfft_unpad_kernel(IrfftArgs a, F
   // inverse transform does).  LDS receives conj(Z): the inverse transform is
   // conj(FFT(conj Z)).
   const int K = hN + 1;
-  for (int i = tid; i < K * P; i += FFT_THREADS) {
-    const int k = i / P, p = i - k * P;
-    const int64_t s = s0 + 2 * p;
-    const int64_t base = k * a.in_k_stride + b * a.in_rhs_stride;
-    cplx<TC> A = {(TC)0, (TC)0}, B = {(TC)0, (TC)0};
-    if (s < a.S) A = {(TC)inb[2 * (base + s)], (TC)inb[2 * (base + s) + 1]};
-    if (s + 1 < a.S) B = {(TC)inb[2 * (base + s + 1)], (TC)inb[2 * (base + s + 1) + 1]};
-    A = round_to(A, a.r_ifft);
-    B = round_to(B, a.r_ifft);
-    if (k == 0 || k == hN) {
-      A.y = (TC)0;
-      B.y = (TC)0;
+  const int nload = K * P;
+  for (int base = tid; base < nload; base += FFT_LOAD_BATCH * TH) {
+    cplx<TC> A[FFT_LOAD_BATCH], B[FFT_LOAD_BATCH];
+#pragma unroll
+    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
+      const int i = base + u * TH;
+      const int k = i / P, p = i - k * P;
+      const int64_t s = s0 + 2 * p;
+      const int64_t off = 2 * (k * a.in_k_stride + b * a.in_rhs_stride + s);
+      A[u] = {(TC)0, (TC)0};
+      B[u] = {(TC)0, (TC)0};
+      if (i < nload && s < a.S) A[u] = {(TC)inb[off], (TC)inb[off + 1]};
+      if (i < nload && s + 1 < a.S) B[u] = {(TC)inb[off + 2], (TC)inb[off + 3]};
     }
-    lds[p * N + k] = {A.x - B.y, -(A.y + B.x)};
-    if (k > 0 && k < hN) lds[p * N + N - k] = {A.x + B.y, A.y - B.x};
+#pragma unroll
+    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
+      const int i = base + u * TH;
+      if (i >= nload) continue;
+      const int k = i / P, p = i - k * P;
+      cplx<TC> Au = round_to(A[u], a.r_ifft), Bu = round_to(B[u], a.r_ifft);
+      if (k == 0 || k == hN) {
+        Au.y = (TC)0;
+        Bu.y = (TC)0;
+      }
+      lds[p * N + k] = {Au.x - Bu.y, -(Au.y + Bu.x)};
+      if (k > 0 && k < hN) lds[p * N + N - k] = {Au.x + Bu.y, Au.y - Bu.x};
+    }
   }
   __syncthreads();
 
-  fft_lds(lds, plan, P, tw);
+  fft_lds<TC, R7, TH, PTS>(lds, plan, P, tw);
 
   const TC inv_n = (TC)(1.0 / (double)N);
-  double* yb = a.y + b * a.y_rhs_stride;
-  for (int i = tid; i < Nt * two_p; i += FFT_THREADS) {
+  double* yb = a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride;
+  for (int i = tid; i < Nt * two_p; i += TH) {
     const int t = i / two_p, j = i - t * two_p;
     const int64_t s = s0 + j;
     if (s >= a.S) continue;
@@ -279,24 +322,48 @@ __global__ __launch_bounds__(FFT_THREADS) void irfft_unpad_kernel(IrfftArgs a, F
 
 // ---- host launchers -----------------------------------------------------------
 
-static int pairs_per_wg(int N, int64_t S) {
-  int P = FFT_POINTS / N;
+// Complex series per workgroup: as many length-N series as fit in PTS points,
+// but no more pairs than there are series.
+static int pairs_per_wg(int N, int64_t S, int pts) {
+  int P = pts / N;
   if (P < 1) P = 1;
   const int64_t need = (S + 1) / 2;
   if (need < P) P = (int)need;
   return P;
 }
 
-template <class TC, class TO>
-static hipError_t rfft_go(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  const int P = pairs_per_wg(plan.N, a.S);
+static bool plan_has7(const FftPlan& plan) {
+  for (int i = 0; i < plan.nst; ++i)
+    if (plan.rad[i] == 7) return true;
+  return false;
+}
+
+// Workgroup shapes: 512 threads over at most 2048 points (one butterfly per
+// thread for radices >= 4, 32 KiB of float64 LDS) up to N = 2048, else over
+// 4096 points.
+constexpr int FFT_TH = 512;
+
+template <class TC, class TO, int PTS>
+static hipError_t rfft_go_shape(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
+  const int P = pairs_per_wg(plan.N, a.S, PTS);
   const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
   const int64_t nwg = npb * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   const size_t lds = (size_t)P * plan.N * sizeof(cplx<TC>);
-  hipLaunchKernelGGL((rfft_pad_kernel<TC, TO>), dim3((unsigned)nwg), dim3(FFT_THREADS), lds, st, a,
-                     plan, reinterpret_cast<const cplx<TC>*>(tw), P, npb);
+  const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
+  if (plan_has7(plan))
+    hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st, a,
+                       plan, t, P, npb);
+  else
+    hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, false, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st, a,
+                       plan, t, P, npb);
   return hipGetLastError();
+}
+
+template <class TC, class TO>
+static hipError_t rfft_go(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
+  if (plan.N <= 2048) return rfft_go_shape<TC, TO, 2048>(a, plan, tw, st);
+  return rfft_go_shape<TC, TO, FFT_POINTS>(a, plan, tw, st);
 }
 
 hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan, const void* tw,
@@ -305,16 +372,27 @@ hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& 
   return rfft_go<float, float>(a, plan, tw, st);
 }
 
-template <class TI, class TC>
-static hipError_t irfft_go(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  const int P = pairs_per_wg(plan.N, a.S);
+template <class TI, class TC, int PTS>
+static hipError_t irfft_go_shape(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
+  const int P = pairs_per_wg(plan.N, a.S, PTS);
   const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
   const int64_t nwg = npb * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   const size_t lds = (size_t)P * plan.N * sizeof(cplx<TC>);
-  hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC>), dim3((unsigned)nwg), dim3(FFT_THREADS), lds, st,
-                     a, plan, reinterpret_cast<const cplx<TC>*>(tw), P, npb);
+  const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
+  if (plan_has7(plan))
+    hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st,
+                       a, plan, t, P, npb);
+  else
+    hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, false, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st,
+                       a, plan, t, P, npb);
   return hipGetLastError();
+}
+
+template <class TI, class TC>
+static hipError_t irfft_go(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
+  if (plan.N <= 2048) return irfft_go_shape<TI, TC, 2048>(a, plan, tw, st);
+  return irfft_go_shape<TI, TC, FFT_POINTS>(a, plan, tw, st);
 }
 
 hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan, const void* tw,

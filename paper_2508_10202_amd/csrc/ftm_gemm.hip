@@ -1,0 +1,426 @@
+// Phase 3 for many right-hand sides: per frequency k the products become
+// complex matrix products,
+//   forward  Y_k[b][r] = sum_c X_k[b][c] Fhat_k[r][c]          (B x Nd)
+//   adjoint  Y_k[b][c] = sum_r X_k[b][r] conj(Fhat_k[r][c])    (B x Nm)
+// computed on the matrix cores (MFMA) with float32 accumulation, from FP32,
+// FP16 or BF16 storage of the spectrum.
+//
+// Forward: complex numbers are stored interleaved, so a row of X_k or Fhat_k
+// is a real row of length 2*ld.  With X' = raw(X) and the two real variants
+// of the spectrum rows Fr' = (re, -im, re, -im, ..) and Fi' = (im, re, ..),
+// Re Y = X' Fr'^T and Im Y = X' Fi'^T: two real products over K' = 2 Nm.
+// A workgroup owns 64 right-hand sides x 64 rows of one frequency; X' is
+// staged through LDS in chunks of 64 reals and shared by the 4 waves, each
+// wave streams its own 16 spectrum rows from HBM.
+//
+// Adjoint: the reduction runs over sensors r; each wave owns 16 columns c and
+// 64 right-hand sides (4 MFMA tiles).  Re Y = xr fr + xi fi and
+// Im Y = xi fr - xr fi, four real MFMAs per step.  X_k is small and shared
+// by every workgroup of the frequency, so it is read through the caches.
+//
+// MFMA lane layouts (checked on gfx950): 16x16x4 f32 -- A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k, D[4 g + v][j] in lane j + 16 g,
+// register v.  16x16x32 f16/bf16 -- lane i + 16 g holds k = 8 g .. 8 g + 7.
+#include "ftm_device.h"
+#include "ftm_kernels.h"
+
+namespace ftm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int GEMM_THREADS = 256;
+constexpr int GEMM_BM = 64;  // right-hand sides per workgroup
+constexpr int FWD_BN = 64;   // spectrum rows per workgroup (forward)
+constexpr int ADJ_BN = 64;   // columns per workgroup (adjoint)
+constexpr int KC = 64;       // reals of K' per LDS chunk (forward)
+constexpr int LDS_PAD = 4;   // floats of padding per LDS row (bank spread)
+
+template <class T>
+__device__ __forceinline__ uint32_t to_bits16(float v);
+template <>
+__device__ __forceinline__ uint32_t to_bits16<__bf16>(float v) {
+  return __float_as_uint(v) >> 16;  // v is a bfloat16 value already: exact
+}
+template <>
+__device__ __forceinline__ uint32_t to_bits16<_Float16>(float v) {
+  return __half_as_ushort(__float2half_rn(v));  // exact for FP16 values
+}
+
+template <class S>
+struct MfmaOf;  // the 16x16x32 half-precision MFMA for a 16-bit storage format
+template <>
+struct MfmaOf<s_bf16> {
+  using half_t = __bf16;
+  using vec = bf16x8;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfmaOf<s_f16> {
+  using half_t = _Float16;
+  using vec = f16x8;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ void store_c(float* y, float v, int r_gemv, int r_next) {
+  *y = round_to(round_to(v, r_gemv), r_next);
+}
+
+// ---------------------------------------------------------------------------
+// forward, FP32 storage: MFMA 16x16x4 f32
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
+  __shared__ float xs[GEMM_BM][KC + LDS_PAD];
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * nrb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / nrb, rb = rem - bb * nrb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * GEMM_BM, r0 = rb * FWD_BN + w * 16;
+  const int kr = 2 * a.ld;  // reals per row
+
+  const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
+  const int64_t xrow = 2 * a.x_rhs_stride;
+  const float* __restrict__ Fk = reinterpret_cast<const float*>(a.F) + 2 * k * a.f_k_stride;
+  const int r_me = min(r0 + l16, a.Nd - 1);  // clamped rows: computed, never stored
+  const float* __restrict__ frow = Fk + (int64_t)r_me * kr;
+
+  f32x4 re[4], im[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  // cooperative X' staging: 64 rows x 64 reals = 1024 float4, 4 per thread
+  const int st_row = threadIdx.x >> 2, st_col = (threadIdx.x & 3) * 4;
+  const int xb = min(b0 + st_row, a.nrhs - 1);
+  const float* __restrict__ xsrc = X + xb * xrow;
+
+  for (int kc = 0; kc < kr; kc += KC) {
+    // stage X'[b0..b0+64)[kc..kc+64) (zero past the row end)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = kc + st_col + 16 * q;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (col < kr) v = *reinterpret_cast<const float4*>(xsrc + col);
+      *reinterpret_cast<float4*>(&xs[st_row][st_col + 16 * q]) = v;
+    }
+    // this wave's spectrum rows, the same 64 reals, in MFMA order
+    uint4 fv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = kc + 16 * s + 4 * g;
+      fv[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float f0 = __uint_as_float(fv[s].x), f1 = __uint_as_float(fv[s].y);
+      const float f2 = __uint_as_float(fv[s].z), f3 = __uint_as_float(fv[s].w);
+      const float br[4] = {f0, -f1, f2, -f3};  // (re, -im, ..)
+      const float bi[4] = {f1, f0, f3, f2};    // (im, re, ..)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float4 xa = *reinterpret_cast<const float4*>(&xs[16 * t + l16][16 * s + 4 * g]);
+        const float av[4] = {xa.x, xa.y, xa.z, xa.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v], br[v], re[t], 0, 0, 0);
+          im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v], bi[v], im[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // D[i = b][j = r]: lane l16 + 16 g holds rows 4 g + v of column l16
+  const int r = r0 + l16;
+  if (r >= a.Nd) return;
+  float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * g + v;
+      if (b < a.nrhs) {
+        float* y = Y + 2 * (b * a.y_rhs_stride + r);
+        store_c(y, re[t][v], a.r_gemv, a.r_next);
+        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward, FP16/BF16 storage: MFMA 16x16x32 (K' = 32 reals per instruction)
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, int nbb, int nrb) {
+  using M = MfmaOf<S>;
+  using H = typename M::half_t;
+  __shared__ uint16_t xs[GEMM_BM][KC + 8];  // X' in 16-bit, 64 reals per chunk
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * nrb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / nrb, rb = rem - bb * nrb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * GEMM_BM, r0 = rb * FWD_BN + w * 16;
+  const int kr = 2 * a.ld;
+
+  const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
+  const int64_t xrow = 2 * a.x_rhs_stride;
+  const uint16_t* __restrict__ Fk = reinterpret_cast<const uint16_t*>(a.F) + 2 * k * a.f_k_stride;
+  const int r_me = min(r0 + l16, a.Nd - 1);
+  const uint16_t* __restrict__ frow = Fk + (int64_t)r_me * kr;
+
+  f32x4 re[4], im[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  const int st_row = threadIdx.x >> 2, st_col = (threadIdx.x & 3) * 4;
+  const int xb = min(b0 + st_row, a.nrhs - 1);
+  const float* __restrict__ xsrc = X + xb * xrow;
+
+  for (int kc = 0; kc < kr; kc += KC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = kc + st_col + 16 * q;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (col < kr) v = *reinterpret_cast<const float4*>(xsrc + col);
+      uint16_t* d = &xs[st_row][st_col + 16 * q];
+      d[0] = (uint16_t)to_bits16<H>(v.x);
+      d[1] = (uint16_t)to_bits16<H>(v.y);
+      d[2] = (uint16_t)to_bits16<H>(v.z);
+      d[3] = (uint16_t)to_bits16<H>(v.w);
+    }
+    uint4 fv[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int col = kc + 32 * s + 8 * g;
+      fv[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      // each 32-bit word is (re | im << 16): Fr' flips the sign of im, Fi' swaps
+      const uint32_t u[4] = {fv[s].x, fv[s].y, fv[s].z, fv[s].w};
+      uint4 ur, ui;
+      uint32_t* pr = reinterpret_cast<uint32_t*>(&ur);
+      uint32_t* pi = reinterpret_cast<uint32_t*>(&ui);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pr[q] = u[q] ^ 0x80000000u;
+        pi[q] = (u[q] >> 16) | (u[q] << 16);
+      }
+      typename M::vec br = *reinterpret_cast<const typename M::vec*>(&ur);
+      typename M::vec bi = *reinterpret_cast<const typename M::vec*>(&ui);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const typename M::vec xa = *reinterpret_cast<const typename M::vec*>(&xs[16 * t + l16][32 * s + 8 * g]);
+        re[t] = M::mma(xa, br, re[t]);
+        im[t] = M::mma(xa, bi, im[t]);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int r = r0 + l16;
+  if (r >= a.Nd) return;
+  float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * g + v;
+      if (b < a.nrhs) {
+        float* y = Y + 2 * (b * a.y_rhs_stride + r);
+        store_c(y, re[t][v], a.r_gemv, a.r_next);
+        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, FP32 storage: MFMA 16x16x4 f32, reduction over r in steps of 4
+// ---------------------------------------------------------------------------
+// X_k (nrhs x Nd complex) is read from global memory (it is small and shared
+// by every workgroup of the frequency, so it stays in cache).
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, int nbb, int ncb) {
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * ncb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / ncb, cb = rem - bb * ncb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN + w * 16;
+  const int c_me = min(c0 + l16, a.ld - 1);
+
+  const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
+  const cplx<float>* __restrict__ Fk = reinterpret_cast<const cplx<float>*>(a.F) + k * a.f_k_stride;
+  int brow[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) brow[t] = min(b0 + 16 * t + l16, a.nrhs - 1);
+
+  f32x4 re[4], im[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  // sensors past Nd contribute zero; their spectrum row index is clamped
+  const int nr = (a.Nd + 3) / 4 * 4;
+#pragma unroll 2
+  for (int r0 = 0; r0 < nr; r0 += 4) {
+    const int r = r0 + g;
+    const int rf = min(r, a.Nd - 1);
+    const cplx<float> f = Fk[(int64_t)rf * a.ld + c_me];
+    cplx<float> x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = r < a.Nd ? X[(int64_t)brow[t] * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t].x, f.x, re[t], 0, 0, 0);
+      re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t].y, f.y, re[t], 0, 0, 0);
+      im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t].y, f.x, im[t], 0, 0, 0);
+      im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x[t].x, f.y, im[t], 0, 0, 0);
+    }
+  }
+
+  const int c = c0 + l16;
+  if (c >= a.Nm) return;
+  float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * g + v;
+      if (b < a.nrhs) {
+        float* y = Y + 2 * (b * a.y_rhs_stride + c);
+        store_c(y, re[t][v], a.r_gemv, a.r_next);
+        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+      }
+    }
+}
+
+// adjoint, FP16/BF16 storage: MFMA 16x16x32, 32 sensors per step.
+// Lane l16 + 16 g gathers its 8 k-values (sensors 8 g .. 8 g + 7) of one
+// column from 8 spectrum rows.
+template <class S>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, int nbb, int ncb) {
+  using M = MfmaOf<S>;
+  using H = typename M::half_t;
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * ncb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / ncb, cb = rem - bb * ncb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN + w * 16;
+  const int c_me = min(c0 + l16, a.ld - 1);
+
+  const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
+  const uint32_t* __restrict__ Fk = reinterpret_cast<const uint32_t*>(a.F) + k * a.f_k_stride;
+  int brow[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) brow[t] = min(b0 + 16 * t + l16, a.nrhs - 1);
+
+  f32x4 re[4], im[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  const int nr = (a.Nd + 31) / 32 * 32;
+  for (int r0 = 0; r0 < nr; r0 += 32) {
+    // B operands: fr and fi of sensors r0 + 8 g + u at column c_me
+    uint32_t fw[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = r0 + 8 * g + u;
+      fw[u] = r < a.Nd ? Fk[(int64_t)r * a.ld + c_me] : 0u;
+    }
+    uint4 ufr, ufi;
+    uint32_t* pr = reinterpret_cast<uint32_t*>(&ufr);
+    uint32_t* pi = reinterpret_cast<uint32_t*>(&ufi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      pr[q] = (fw[2 * q] & 0xffffu) | (fw[2 * q + 1] << 16);
+      pi[q] = (fw[2 * q] >> 16) | (fw[2 * q + 1] & 0xffff0000u);
+    }
+    const typename M::vec fr = *reinterpret_cast<const typename M::vec*>(&ufr);
+    const typename M::vec fi = *reinterpret_cast<const typename M::vec*>(&ufi);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      // A operands: x of right-hand side brow[t] at the same 8 sensors
+      uint4 uxr, uxi, uxn;
+      uint32_t* qr = reinterpret_cast<uint32_t*>(&uxr);
+      uint32_t* qi = reinterpret_cast<uint32_t*>(&uxi);
+      uint32_t* qn = reinterpret_cast<uint32_t*>(&uxn);
+      const cplx<float>* xr = X + (int64_t)brow[t] * a.x_rhs_stride;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // sensors past Nd contribute zero
+        const int r = r0 + 8 * g + 2 * q;
+        const cplx<float> z = {0.f, 0.f};
+        const cplx<float> x0 = r < a.Nd ? xr[r] : z, x1 = r + 1 < a.Nd ? xr[r + 1] : z;
+        qr[q] = to_bits16<H>(x0.x) | (to_bits16<H>(x1.x) << 16);
+        qi[q] = to_bits16<H>(x0.y) | (to_bits16<H>(x1.y) << 16);
+        qn[q] = qr[q] ^ 0x80008000u;
+      }
+      const typename M::vec vxr = *reinterpret_cast<const typename M::vec*>(&uxr);
+      const typename M::vec vxi = *reinterpret_cast<const typename M::vec*>(&uxi);
+      const typename M::vec vxn = *reinterpret_cast<const typename M::vec*>(&uxn);
+      re[t] = M::mma(vxr, fr, re[t]);
+      re[t] = M::mma(vxi, fi, re[t]);
+      im[t] = M::mma(vxi, fr, im[t]);
+      im[t] = M::mma(vxn, fi, im[t]);
+    }
+  }
+
+  const int c = c0 + l16;
+  if (c >= a.Nm) return;
+  float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * g + v;
+      if (b < a.nrhs) {
+        float* y = Y + 2 * (b * a.y_rhs_stride + c);
+        store_c(y, re[t][v], a.r_gemv, a.r_next);
+        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+      }
+    }
+}
+
+// ---- host launchers -----------------------------------------------------------
+
+hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st) {
+  const int nbb = (a.nrhs + GEMM_BM - 1) / GEMM_BM, nrb = (a.Nd + FWD_BN - 1) / FWD_BN;
+  const int64_t nwg = (int64_t)a.K * nbb * nrb;
+  if (nwg <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
+  switch (fdt) {
+    case DT_F32: hipLaunchKernelGGL(gemm_fwd_f32_kernel, grid, block, 0, st, a, nbb, nrb); break;
+    case DT_F16: hipLaunchKernelGGL(gemm_fwd_h_kernel<s_f16>, grid, block, 0, st, a, nbb, nrb); break;
+    case DT_BF16: hipLaunchKernelGGL(gemm_fwd_h_kernel<s_bf16>, grid, block, 0, st, a, nbb, nrb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_adj(int fdt, const GemvArgs& a, hipStream_t st) {
+  const int nbb = (a.nrhs + GEMM_BM - 1) / GEMM_BM, ncb = (a.Nm + ADJ_BN - 1) / ADJ_BN;
+  const int64_t nwg = (int64_t)a.K * nbb * ncb;
+  if (nwg <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
+  switch (fdt) {
+    case DT_F32: hipLaunchKernelGGL(gemm_adj_f32_kernel, grid, block, 0, st, a, nbb, ncb); break;
+    case DT_F16: hipLaunchKernelGGL(gemm_adj_h_kernel<s_f16>, grid, block, 0, st, a, nbb, ncb); break;
+    case DT_BF16: hipLaunchKernelGGL(gemm_adj_h_kernel<s_bf16>, grid, block, 0, st, a, nbb, ncb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ftm

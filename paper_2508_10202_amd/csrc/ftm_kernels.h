@@ -9,9 +9,16 @@ namespace ftm {
 
 constexpr int MAX_STAGES = 16;
 // Largest number of complex points one FFT workgroup holds in LDS: P series
-// of length N with P * N <= FFT_POINTS (64 KiB of float64 complex).
-constexpr int FFT_POINTS = 4096;
-constexpr int FFT_THREADS = 256;
+// of length N with P * N <= FFT_POINTS (64 KiB of float64 complex), and the
+// workgroup size of the FFT kernels.
+#ifndef FTM_FFT_POINTS
+#define FTM_FFT_POINTS 4096
+#endif
+#ifndef FTM_FFT_THREADS
+#define FTM_FFT_THREADS 512  // kept for reference; the launchers use FFT_TH
+#endif
+constexpr int FFT_POINTS = FTM_FFT_POINTS;
+constexpr int FFT_THREADS = FTM_FFT_THREADS;
 
 // Mixed-radix plan of a length-N complex FFT: N = rad[0] * rad[1] * ...
 struct FftPlan {
@@ -23,8 +30,13 @@ struct FftPlan {
 // Phases 1+2 (or the setup transform of F): real series x[b][t][s] (t < Nt,
 // s < S), zero padded to N = plan.N, transformed, bins k = 0 .. N/2 written to
 // out[k * out_k_stride + b * out_rhs_stride + (s / ncol) * ld_row + s % ncol].
+// With xptr set (device array of nrhs pointers) right-hand side b is read from
+// xptr[b] instead of x + b * x_rhs_stride.  Columns S .. pad_to-1 of every
+// output row are written as zeros (pad_to <= S: none).
 struct RfftArgs {
   const double* x;
+  const double* const* xptr;
+  int64_t pad_to;
   int64_t x_rhs_stride, x_row_stride;
   int64_t S;
   int Nt, nrhs;
@@ -41,6 +53,7 @@ struct IrfftArgs {
   int64_t S;
   int Nt, nrhs;
   double* y;
+  double* const* yptr;  // optional per-right-hand-side output pointers
   int64_t y_rhs_stride, y_row_stride;
   int r_ifft, r_unpad;
 };
@@ -68,6 +81,10 @@ hipError_t launch_gemv_fwd(int fdt, bool acc64, bool in64, bool out64, const Gem
                            hipStream_t st);
 hipError_t launch_gemv_adj(int fdt, bool acc64, bool in64, bool out64, const GemvArgs& a,
                            hipStream_t st);
+// Phase 3 for many right-hand sides on the matrix cores (FP32/FP16/BF16
+// storage, float32 accumulation; float32 transformed vectors).
+hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st);
+hipError_t launch_gemm_adj(int fdt, const GemvArgs& a, hipStream_t st);
 // Round a float64 complex spectrum to storage format dt (n complex numbers).
 hipError_t launch_store_spectrum(const void* src, int dt, void* dst, int64_t n, hipStream_t st);
 // Widen rows x ncol complex numbers of storage format dt (row stride ld) to a

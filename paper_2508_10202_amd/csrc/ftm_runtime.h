@@ -1,0 +1,109 @@
+// Host runtime internals shared by the C ABI (ftm_api.hip) and the serving
+// scheduler (ftm_server.hip): the operator object, error reporting and the
+// stream-ordered three-kernel chain of one matvec.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ftm.h"
+#include "ftm_kernels.h"
+
+namespace ftm_rt {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+// Device workspace of one matvec: the transformed input and output vectors,
+// [K][nrhs][ld] complex each, float64-sized (float32 intermediates use the
+// first half).
+struct Workspace {
+  void* mhat = nullptr;
+  void* dhat = nullptr;
+};
+
+// Inputs and outputs of one matvec: contiguous [nrhs][Nt][n] arrays, or
+// device arrays of nrhs pointers (one [Nt][n] block each) when xptr/yptr are
+// set.
+struct MatvecIO {
+  const double* x = nullptr;
+  double* y = nullptr;
+  const double* const* xptr = nullptr;
+  double* const* yptr = nullptr;
+};
+
+}  // namespace ftm_rt
+
+struct ftm_operator_s {
+  int64_t Nt = 0, Nd = 0, Nm = 0, L = 0, K = 0;
+  int ldm = 0, ldd = 0;  // padded column counts of spectra and workspaces
+  int device = 0;
+  int64_t max_rhs = 1;
+  ftm::FftPlan plan{};
+  ftm_rt::DevBuf tw64, tw32;  // exp(-2 pi i e / L), e = 0 .. L-1
+  ftm_rt::DevBuf spec[4];     // Fhat[K][Nd][ldm] per storage format
+  ftm_rt::DevBuf mhat, dhat;  // the operator's own workspace, sized for max_rhs
+  ftm_precision fwd{}, adj{};
+  int rhs_mode = FTM_RHS_AUTO;
+  int64_t gemm_min_rhs = 2;
+
+  // instrumentation: events around the three kernels of each recorded call
+  bool profiling = false;
+  struct Rec {
+    int dir;
+    hipEvent_t ev[4];
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+
+  size_t bytes() const {
+    size_t b = tw64.n + tw32.n + mhat.n + dhat.n;
+    for (const auto& s : spec) b += s.n;
+    return b;
+  }
+  // workspace bytes a matvec of nrhs right-hand sides needs
+  size_t workspace_bytes(int64_t nrhs) const {
+    return (size_t)K * nrhs * (ldm + ldd) * 16 + 512;
+  }
+};
+
+namespace ftm_rt {
+
+ftm_status fail(ftm_status s, const std::string& msg);
+ftm_status fail_hip(const char* what, hipError_t e);
+
+#define FTM_HIP(expr)                                         \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return ftm_rt::fail_hip(#expr, e_); \
+  } while (0)
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old_) == hipSuccess && old_ != dev) {
+      if (hipSetDevice(dev) == hipSuccess) switched_ = true;
+    }
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(old_);
+  }
+
+ private:
+  int old_ = 0;
+  bool switched_ = false;
+};
+
+// Split a workspace block of op->workspace_bytes(nrhs) bytes.
+Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs);
+
+// Enqueue one matvec (phases 1-5) on st.  No argument checks: callers
+// validate.
+ftm_status run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io, int64_t nrhs, const Workspace& ws,
+                      hipStream_t st);
+
+}  // namespace ftm_rt

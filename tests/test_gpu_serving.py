@@ -1,0 +1,131 @@
+"""Serving loop on the GPU: continuous batching, budget admission, and that
+every result is the same alone and in the mix."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Shape, make_F, normal
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ops():
+    import torch
+    from paper_2508_10202_amd import Operator
+    shapes = [Shape(40, 12, 300, decay=30.0), Shape(64, 20, 500), Shape(25, 7, 130, decay=None)]
+    Fs = [make_F(s, 500 + i) for i, s in enumerate(shapes)]
+    out = []
+    for s, F in zip(shapes, Fs):
+        out.append((s, F, Operator(torch.from_numpy(F).cuda(), spectra=("s",))))
+    yield out
+    for _, _, op in out:
+        op.close()
+
+
+def _requests(ops, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        k = int(rng.integers(len(ops)))
+        adj = bool(rng.integers(2))
+        nrhs = int(rng.integers(1, 9))
+        s = ops[k][0]
+        x = normal((nrhs, s.Nt, s.Nd if adj else s.Nm), 10_000 * seed + i)
+        reqs.append((k, adj, x))
+    return reqs
+
+
+def _alone(op, adj, x):
+    import torch
+    xt = torch.from_numpy(x).cuda()
+    return (op.rmatvec(xt) if adj else op.matvec(xt)).cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["ddddd", "sssss"])
+def test_mix_equals_alone(gpu, ops, prec):
+    """A burst of mixed requests (3 operators, both directions, 1-8 vectors)
+    through the server: each output equals the oracle and the request run
+    alone -- bitwise in float64 (one product per vector either way), within
+    the configuration's tolerance in float32 (a batch may take the GEMM)."""
+    import torch
+    from paper_2508_10202_amd import Server
+    for _, _, op in ops:
+        op.set_precision(fwd=prec, adj=prec)
+    reqs = _requests(ops, 60, seed=1 if prec == "ddddd" else 2)
+    xs = [torch.from_numpy(x).cuda() for _, _, x in reqs]
+    torch.cuda.synchronize()
+    with Server(workspace_budget=1 << 30, n_slots=3, max_batch_rhs=32) as srv:
+        tickets = [srv.submit(ops[k][2], xs[i], adjoint=adj) for i, (k, adj, _) in enumerate(reqs)]
+        lat = [srv.wait(t, timeout=60) for t, _ in tickets]
+        st = srv.stats()
+    _say(f"  serving {prec}: {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["coalesced_requests"] > 0            # requests did share batches
+    assert all(l > 0 for l in lat)
+    tol = 1e-12 if prec == "ddddd" else 2e-5
+    n_bitwise = 0
+    for (k, adj, x), (t, y) in zip(reqs, tickets):
+        s, F, op = ops[k]
+        got = y.cpu().numpy()
+        ref = oracle.adjoint(F, x) if adj else oracle.forward(F, x)
+        assert oracle.relative_l2(got, ref) <= tol
+        alone = _alone(op, adj, x)
+        if prec == "ddddd":
+            assert np.array_equal(got, alone)
+        else:
+            assert oracle.relative_l2(got, alone) <= tol
+        n_bitwise += int(np.array_equal(got, alone))
+    _say(f"  {n_bitwise}/{len(reqs)} bitwise equal to the lone run")
+    for _, _, op in ops:
+        op.set_precision(fwd="ddddd", adj="ddddd")
+
+
+def test_tiny_budget_queues_instead_of_failing(gpu, ops):
+    """A budget that holds only one of the largest requests at a time: requests
+    wait for workspace (budget_waits > 0), never fail, never exceed it."""
+    import torch
+    from paper_2508_10202_amd import Server
+    need = max(_ws(op, 8) for _, _, op in ops)
+    reqs = _requests(ops, 40, seed=3)
+    xs = [torch.from_numpy(x).cuda() for _, _, x in reqs]
+    torch.cuda.synchronize()
+    with Server(workspace_budget=need, n_slots=4, max_batch_rhs=8) as srv:
+        tickets = [srv.submit(ops[k][2], xs[i], adjoint=adj) for i, (k, adj, _) in enumerate(reqs)]
+        for t, _ in tickets:
+            srv.wait(t, timeout=60)
+        st = srv.stats()
+    _say(f"  tiny budget: {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["budget_waits"] > 0
+    assert st["peak_workspace_bytes"] <= need
+    for (k, adj, x), (t, y) in zip(reqs, tickets):
+        s, F, op = ops[k]
+        ref = oracle.adjoint(F, x) if adj else oracle.forward(F, x)
+        assert oracle.relative_l2(y.cpu().numpy(), ref) <= 1e-12
+
+
+def _ws(op, nrhs):
+    """Workspace bytes of one batch, as the library sizes it."""
+    K = op.Nt + 1
+    ldm, ldd = (op.Nm + 7) // 8 * 8, (op.Nd + 7) // 8 * 8
+    return K * nrhs * (ldm + ldd) * 16 + 512 + 512
+
+
+def test_request_beyond_budget_is_rejected(gpu, ops):
+    import torch
+    from paper_2508_10202_amd import FtmError, Server
+    s, F, op = ops[1]
+    x = torch.zeros((8, s.Nt, s.Nm), dtype=torch.float64, device="cuda")
+    with Server(workspace_budget=_ws(op, 2), n_slots=1, max_batch_rhs=8) as srv:
+        with pytest.raises(FtmError) as ei:
+            srv.submit(op, x)
+        assert ei.value.status == 4            # FTM_ERR_BUDGET
+        t, y = srv.submit(op, x[:1])           # one vector fits
+        srv.wait(t, timeout=60)

@@ -93,3 +93,19 @@ def test_precision_strings():
     for bad in ("dddd", "dxddd", "ddddd+a16"):
         with pytest.raises(ValueError):
             Precision.parse(bad)
+
+
+def test_server_rejects_bad_arguments_without_a_gpu(L):
+    from paper_2508_10202_amd._lib import ERR_INVALID
+    h = ctypes.c_void_p()
+    assert L.ftm_server_create(None, 1 << 20, 2, 8) == ERR_INVALID
+    assert L.ftm_server_create(ctypes.byref(h), 100, 2, 8) == ERR_INVALID     # budget < 4 KiB
+    assert L.ftm_server_create(ctypes.byref(h), 1 << 20, 0, 8) == ERR_INVALID
+    assert L.ftm_server_create(ctypes.byref(h), 1 << 20, 17, 8) == ERR_INVALID
+    assert L.ftm_server_create(ctypes.byref(h), 1 << 20, 2, 0) == ERR_INVALID
+    t = ctypes.c_uint64()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ftm_server_submit(None, fake, 0, fake, fake, 1, None, ctypes.byref(t)) == ERR_INVALID
+    done = ctypes.c_int32()
+    assert L.ftm_server_poll(None, 1, ctypes.byref(done), None) == ERR_INVALID
+    assert L.ftm_server_destroy(None) == 0
