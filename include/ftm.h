@@ -121,6 +121,28 @@ ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode);
 /* Smallest nrhs for which FTM_RHS_AUTO uses the GEMM (>= 2; default 2). */
 ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs);
 
+/* Autotuning of the phase-3 tile shape: time each of the matrix-vector
+ * kernels' variants for both directions at the operator's current precision
+ * configuration (one vector, reps timed runs each, on scratch inputs) and
+ * keep the fastest.  Synchronises the stream.  The choice is kept per
+ * direction and storage format; ftm_get_tuning / ftm_set_tuning read and set
+ * it (for a persistent tuning cache kept by the caller). */
+ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream);
+ftm_status ftm_get_tuning(ftm_operator op, int32_t* fwd_variant, int32_t* adj_variant, double* fwd_ms,
+                          double* adj_ms);
+ftm_status ftm_set_tuning(ftm_operator op, int32_t fwd_variant, int32_t adj_variant);
+
+/* HIP graph of one matvec with fixed buffers (x, y as for ftm_matvec or
+ * ftm_rmatvec; adjoint != 0 selects F^T).  Launching replays the three
+ * kernels with one call.  The graph uses the operator's workspace: replays
+ * must not overlap other calls on the operator.  The graph is bound to the
+ * operator's precision and tuning at capture time. */
+typedef struct ftm_graph_s* ftm_graph;
+ftm_status ftm_graph_create(ftm_graph* out, ftm_operator op, int32_t adjoint, const double* x, double* y,
+                            int64_t nrhs);
+ftm_status ftm_graph_launch(ftm_graph g, void* stream);
+ftm_status ftm_graph_destroy(ftm_graph g);
+
 /* Copy bins k0 .. k0+nk-1 of the stored spectrum in storage precision
  * `which` (widened to float64) to out: device float64 [nk][Nd][Nm][2]
  * (real, imaginary).  Fhat_k = sum_{t<Nt} F_t exp(-2 pi i k t / L). */

@@ -23,7 +23,8 @@ RHS_AUTO, RHS_GEMV, RHS_GEMM = range(3)
 # Every symbol include/ftm.h declares.
 EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
            "ftm_get_spectrum", "ftm_operator_info", "ftm_profile_enable", "ftm_profile_read",
-           "ftm_set_rhs_mode", "ftm_set_gemm_crossover",
+           "ftm_set_rhs_mode", "ftm_set_gemm_crossover", "ftm_autotune", "ftm_get_tuning",
+           "ftm_set_tuning", "ftm_graph_create", "ftm_graph_launch", "ftm_graph_destroy",
            "ftm_server_create", "ftm_server_submit", "ftm_server_poll", "ftm_server_wait",
            "ftm_server_latencies", "ftm_server_get_stats", "ftm_server_destroy",
            "ftm_destroy_operator",
@@ -74,6 +75,13 @@ def lib() -> ctypes.CDLL:
         "ftm_profile_enable": [vp, i32],
         "ftm_set_rhs_mode": [vp, i32],
         "ftm_set_gemm_crossover": [vp, i64],
+        "ftm_autotune": [vp, i32, vp],
+        "ftm_get_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)],
+        "ftm_set_tuning": [vp, i32, i32],
+        "ftm_graph_create": [ctypes.POINTER(vp), vp, i32, vp, vp, i64],
+        "ftm_graph_launch": [vp, vp],
+        "ftm_graph_destroy": [vp],
         "ftm_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32],
         "ftm_destroy_operator": [vp],
         "ftm_server_create": [ctypes.POINTER(vp), ctypes.c_size_t, i32, i64],

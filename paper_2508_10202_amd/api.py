@@ -176,6 +176,58 @@ class Operator:
     def set_gemm_crossover(self, min_rhs: int) -> None:
         check(lib().ftm_set_gemm_crossover(self.handle, int(min_rhs)), "ftm_set_gemm_crossover")
 
+    def autotune(self, reps: int = 10, cache: str | None = None, stream=None) -> dict:
+        """Pick the phase-3 tile variants by timing them on this operator at its
+        current precision (``ftm_autotune``).  With ``cache`` (a JSON file),
+        an earlier choice for the same device, shape and precision is reused
+        instead of timing again, and new choices are stored."""
+        import json
+        import os
+        key = f"{torch.cuda.get_device_name(self.device)}|{self.Nt}x{self.Nd}x{self.Nm}|{self.fwd}|{self.adj}"
+        db = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                db = json.load(fh)
+        if key in db:
+            check(lib().ftm_set_tuning(self.handle, db[key]["fwd_variant"], db[key]["adj_variant"]),
+                  "ftm_set_tuning")
+            return dict(db[key], cached=True)
+        with torch.cuda.device(self.device):
+            check(lib().ftm_autotune(self.handle, int(reps), _stream_ptr(stream)), "ftm_autotune")
+        rec = self.tuning()
+        if cache:
+            db[key] = rec
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(db, fh, indent=1)
+            os.replace(tmp, cache)
+        return dict(rec, cached=False)
+
+    def tuning(self) -> dict:
+        fv, av = ctypes.c_int32(), ctypes.c_int32()
+        fm, am = ctypes.c_double(), ctypes.c_double()
+        check(lib().ftm_get_tuning(self.handle, ctypes.byref(fv), ctypes.byref(av), ctypes.byref(fm),
+                                   ctypes.byref(am)), "ftm_get_tuning")
+        return {"fwd_variant": fv.value, "adj_variant": av.value, "fwd_ms": fm.value, "adj_ms": am.value}
+
+    def set_tuning(self, fwd_variant: int, adj_variant: int) -> None:
+        check(lib().ftm_set_tuning(self.handle, int(fwd_variant), int(adj_variant)), "ftm_set_tuning")
+
+    def graph(self, x: torch.Tensor, adjoint: bool = False, out=None) -> "Graph":
+        """Capture one matvec with fixed buffers into a HIP graph (``ftm_graph_create``)."""
+        n_in, n_out = (self.Nd, self.Nm) if adjoint else (self.Nm, self.Nd)
+        x = _dev_f64(x, "x")
+        xb = x.unsqueeze(0) if x.dim() == 2 else x
+        if tuple(xb.shape[1:]) != (self.Nt, n_in):
+            raise ValueError("input has the wrong shape")
+        y = out if out is not None else torch.empty((xb.shape[0], self.Nt, n_out), dtype=torch.float64,
+                                                    device=x.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().ftm_graph_create(ctypes.byref(h), self.handle, 1 if adjoint else 0, xb.data_ptr(),
+                                         y.data_ptr(), xb.shape[0]), "ftm_graph_create")
+        return Graph(h, self, xb, y)
+
     def profile(self, enable: bool = True) -> None:
         """Record HIP events around each kernel of every following call."""
         check(lib().ftm_profile_enable(self.handle, 1 if enable else 0), "ftm_profile_enable")
@@ -208,6 +260,30 @@ class Operator:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Graph:
+    """A captured matvec; ``launch()`` replays it on a stream, ``y`` is its output."""
+
+    def __init__(self, h, op, x, y):
+        self._h, self.op, self.x, self.y = h, op, x, y
+
+    def launch(self, stream=None) -> torch.Tensor:
+        with torch.cuda.device(self.op.device):
+            check(lib().ftm_graph_launch(self._h, _stream_ptr(stream)), "ftm_graph_launch")
+        return self.y
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.op.device)
+            lib().ftm_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

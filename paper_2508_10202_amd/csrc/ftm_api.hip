@@ -253,6 +253,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io,
   ga.y_rhs_stride = ldy;
   ga.r_gemv = p.gemv;
   ga.r_next = p.ifft;
+  ga.variant = op->variant[adjoint ? 1 : 0][p.gemv];
   const bool acc64 = p.accum == DT_F64;
   prof.mark(1);
   // many right-hand sides: one pass of the spectrum through the matrix cores
@@ -513,6 +514,151 @@ ftm_status ftm_profile_read(ftm_operator op, double* ms, int64_t* counts, int32_
         if (e) op->event_pool.push_back(e);
     op->recs.clear();
   }
+  return FTM_OK;
+}
+
+ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (reps < 1 || reps > 1000) return fail(FTM_ERR_INVALID, "reps must be in [1, 1000]");
+  DeviceGuard g(op->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t nx = (size_t)op->Nt * (size_t)(op->Nm > op->Nd ? op->Nm : op->Nd);
+  DevBuf x, y;
+  ftm_status s;
+  if ((s = dev_alloc(&x, nx * 8)) != FTM_OK) return s;
+  if ((s = dev_alloc(&y, nx * 8)) != FTM_OK) {
+    dev_free(&x);
+    return s;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto done = [&](ftm_status r) {
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(&x);
+    dev_free(&y);
+    return r;
+  };
+  // any finite pattern does: the kernels' speed does not depend on the values
+  if (hipMemsetAsync(x.p, 0x3f, x.n, st) != hipSuccess) return done(fail(FTM_ERR_HIP, "hipMemsetAsync"));
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return done(fail(FTM_ERR_HIP, "hipEventCreate"));
+  const bool prof = op->profiling;
+  op->profiling = false;
+  ftm_rt::Workspace ws;
+  ws.mhat = op->mhat.p;
+  ws.dhat = op->dhat.p;
+  for (int dir = 0; dir < 2; ++dir) {
+    const int dt = (dir ? op->adj : op->fwd).gemv;
+    ftm_rt::MatvecIO io;
+    io.x = reinterpret_cast<const double*>(x.p);
+    io.y = reinterpret_cast<double*>(y.p);
+    int best = 0;
+    double best_ms = 1e300;
+    for (int v = 0; v < GEMV_VARIANTS; ++v) {
+      op->variant[dir][dt] = v;
+      if ((s = ftm_rt::run_matvec(op, dir == 1, io, 1, ws, st)) != FTM_OK) {
+        op->profiling = prof;
+        return done(s);
+      }
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r) ftm_rt::run_matvec(op, dir == 1, io, 1, ws, st);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        op->profiling = prof;
+        return done(fail(FTM_ERR_HIP, "hipEventSynchronize"));
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / reps < best_ms) {
+        best_ms = ms / reps;
+        best = v;
+      }
+    }
+    op->variant[dir][dt] = best;
+    op->tuned_ms[dir] = best_ms;
+  }
+  op->profiling = prof;
+  return done(FTM_OK);
+}
+
+ftm_status ftm_get_tuning(ftm_operator op, int32_t* fwd_variant, int32_t* adj_variant, double* fwd_ms,
+                          double* adj_ms) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (fwd_variant) *fwd_variant = op->variant[0][op->fwd.gemv];
+  if (adj_variant) *adj_variant = op->variant[1][op->adj.gemv];
+  if (fwd_ms) *fwd_ms = op->tuned_ms[0];
+  if (adj_ms) *adj_ms = op->tuned_ms[1];
+  return FTM_OK;
+}
+
+ftm_status ftm_set_tuning(ftm_operator op, int32_t fwd_variant, int32_t adj_variant) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (fwd_variant < 0 || fwd_variant >= GEMV_VARIANTS || adj_variant < 0 || adj_variant >= GEMV_VARIANTS)
+    return fail(FTM_ERR_INVALID, "variant out of range");
+  op->variant[0][op->fwd.gemv] = fwd_variant;
+  op->variant[1][op->adj.gemv] = adj_variant;
+  return FTM_OK;
+}
+
+struct ftm_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+ftm_status ftm_graph_create(ftm_graph* out, ftm_operator op, int32_t adjoint, const double* x, double* y,
+                            int64_t nrhs) {
+  if (!out) return fail(FTM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!op || !x || !y) return fail(FTM_ERR_INVALID, "NULL argument");
+  if (nrhs < 1 || nrhs > op->max_rhs) return fail(FTM_ERR_INVALID, "nrhs must be in [1, max_rhs]");
+  DeviceGuard g(op->device);
+  hipStream_t cs = nullptr;
+  FTM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  ftm_graph gr = new ftm_graph_s();
+  gr->device = op->device;
+  const bool prof = op->profiling;
+  op->profiling = false;  // no event records inside the graph
+  ftm_rt::MatvecIO io;
+  io.x = x;
+  io.y = y;
+  ftm_rt::Workspace ws;
+  ws.mhat = op->mhat.p;
+  ws.dhat = op->dhat.p;
+  ftm_status s = FTM_OK;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = ftm_rt::run_matvec(op, adjoint != 0, io, nrhs, ws, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &gr->graph);
+    if (s == FTM_OK && e2 != hipSuccess) e = e2;
+  }
+  op->profiling = prof;
+  if (e == hipSuccess && s == FTM_OK) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || s != FTM_OK) {
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return s != FTM_OK ? s : fail_hip("graph capture", e);
+  }
+  *out = gr;
+  return FTM_OK;
+}
+
+ftm_status ftm_graph_launch(ftm_graph g, void* stream) {
+  if (!g) return fail(FTM_ERR_INVALID, "graph is NULL");
+  DeviceGuard dg(g->device);
+  FTM_HIP(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
+  return FTM_OK;
+}
+
+ftm_status ftm_graph_destroy(ftm_graph g) {
+  if (!g) return FTM_OK;
+  DeviceGuard dg(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return FTM_OK;
 }
 

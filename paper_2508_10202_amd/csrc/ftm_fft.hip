@@ -239,8 +239,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
     X = round_to(round_to(X, a.r_fft), a.r_next);
     const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + (s / a.ncol) * a.ld_row + s % a.ncol;
-    outb[2 * off] = (TO)X.x;
-    outb[2 * off + 1] = (TO)X.y;
+    reinterpret_cast<cplx<TO>*>(outb)[off] = {(TO)X.x, (TO)X.y};  // one 16/8-byte store
   }
   // the last pair block of a right-hand side also clears the padding columns
   // (the products read them, multiplied by the spectrum's zero padding)
@@ -249,8 +248,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     for (int i = tid; i < K * npad; i += TH) {
       const int k = i / npad;
       const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + a.S + (i - k * npad);
-      outb[2 * off] = (TO)0;
-      outb[2 * off + 1] = (TO)0;
+      reinterpret_cast<cplx<TO>*>(outb)[off] = {(TO)0, (TO)0};
     }
   }
 }
@@ -341,7 +339,14 @@ static bool plan_has7(const FftPlan& plan) {
 // Workgroup shapes: 512 threads over at most 2048 points (one butterfly per
 // thread for radices >= 4, 32 KiB of float64 LDS) up to N = 2048, else over
 // 4096 points.
-constexpr int FFT_TH = 512;
+#ifndef FTM_FFT_TH
+#define FTM_FFT_TH 512
+#endif
+#ifndef FTM_FFT_SMALL_PTS
+#define FTM_FFT_SMALL_PTS 2048
+#endif
+constexpr int FFT_TH = FTM_FFT_TH;
+constexpr int FFT_SMALL_PTS = FTM_FFT_SMALL_PTS;
 
 template <class TC, class TO, int PTS>
 static hipError_t rfft_go_shape(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
@@ -362,7 +367,7 @@ static hipError_t rfft_go_shape(const RfftArgs& a, const FftPlan& plan, const vo
 
 template <class TC, class TO>
 static hipError_t rfft_go(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  if (plan.N <= 2048) return rfft_go_shape<TC, TO, 2048>(a, plan, tw, st);
+  if (plan.N <= FFT_SMALL_PTS) return rfft_go_shape<TC, TO, FFT_SMALL_PTS>(a, plan, tw, st);
   return rfft_go_shape<TC, TO, FFT_POINTS>(a, plan, tw, st);
 }
 
@@ -391,7 +396,7 @@ static hipError_t irfft_go_shape(const IrfftArgs& a, const FftPlan& plan, const 
 
 template <class TI, class TC>
 static hipError_t irfft_go(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  if (plan.N <= 2048) return irfft_go_shape<TI, TC, 2048>(a, plan, tw, st);
+  if (plan.N <= FFT_SMALL_PTS) return irfft_go_shape<TI, TC, FFT_SMALL_PTS>(a, plan, tw, st);
   return irfft_go_shape<TI, TC, FFT_POINTS>(a, plan, tw, st);
 }
 

@@ -67,8 +67,10 @@ struct MfmaOf<s_f16> {
   }
 };
 
-__device__ __forceinline__ void store_c(float* y, float v, int r_gemv, int r_next) {
-  *y = round_to(round_to(v, r_gemv), r_next);
+// one complex output, rounded to the product's format then the next phase's
+__device__ __forceinline__ void store_c(float* y, float re, float im, int r_gemv, int r_next) {
+  *reinterpret_cast<float2*>(y) = make_float2(round_to(round_to(re, r_gemv), r_next),
+                                              round_to(round_to(im, r_gemv), r_next));
 }
 
 // ---------------------------------------------------------------------------
@@ -148,8 +150,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_f32_kernel(GemvArgs a, 
       const int b = b0 + 16 * t + 4 * g + v;
       if (b < a.nrhs) {
         float* y = Y + 2 * (b * a.y_rhs_stride + r);
-        store_c(y, re[t][v], a.r_gemv, a.r_next);
-        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
       }
     }
 }
@@ -238,8 +239,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
       const int b = b0 + 16 * t + 4 * g + v;
       if (b < a.nrhs) {
         float* y = Y + 2 * (b * a.y_rhs_stride + r);
-        store_c(y, re[t][v], a.r_gemv, a.r_next);
-        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
       }
     }
 }
@@ -298,8 +298,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
       const int b = b0 + 16 * t + 4 * g + v;
       if (b < a.nrhs) {
         float* y = Y + 2 * (b * a.y_rhs_stride + c);
-        store_c(y, re[t][v], a.r_gemv, a.r_next);
-        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
       }
     }
 }
@@ -387,8 +386,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
       const int b = b0 + 16 * t + 4 * g + v;
       if (b < a.nrhs) {
         float* y = Y + 2 * (b * a.y_rhs_stride + c);
-        store_c(y, re[t][v], a.r_gemv, a.r_next);
-        store_c(y + 1, im[t][v], a.r_gemv, a.r_next);
+        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
       }
     }
 }

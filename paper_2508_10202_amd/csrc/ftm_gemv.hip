@@ -86,8 +86,9 @@ template <bool NT, class TA, class TO>
 __device__ __forceinline__ void store_out(cplx<TO>* p, cplx<TA> v, int r_gemv, int r_next) {
   v = round_to(round_to(v, r_gemv), r_next);
   if constexpr (NT) {
-    __builtin_nontemporal_store((TO)v.x, &p->x);
-    __builtin_nontemporal_store((TO)v.y, &p->y);
+    typedef TO v2 __attribute__((ext_vector_type(2)));
+    const v2 w = {(TO)v.x, (TO)v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));  // one 16/8-byte store
   } else {
     *p = {(TO)v.x, (TO)v.y};
   }
@@ -234,28 +235,47 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_adj_kernel(GemvArgs a, int 
 
 // ---- host launchers -----------------------------------------------------------
 
-template <class S, class TA, class TI, class TO>
-static hipError_t fwd_go(const GemvArgs& a, hipStream_t st) {
-  const int R = FWD_ROWS;
+// Tile-shape variants (chosen per operator by the autotuner):
+//   forward  0: 4 rows per workgroup (default), 1: 2 rows, 2: 8 rows
+//   adjoint  0: 4 waves split the rows (default), 1: 2 waves split the rows
+//            (2 column groups), 2: 4 waves split the rows, 2 chunks per lane
+template <class S, class TA, class TI, class TO, int R>
+static hipError_t fwd_go_r(const GemvArgs& a, hipStream_t st) {
   const int nrb = (a.Nd + R - 1) / R;
   const int64_t nwg = (int64_t)a.nrhs * a.K * nrb;
   if (nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemv_fwd_kernel<S, TA, TI, TO, FWD_ROWS>), dim3((unsigned)nwg), dim3(GEMV_THREADS),
-                     0, st, a, nrb);
+  hipLaunchKernelGGL((gemv_fwd_kernel<S, TA, TI, TO, R>), dim3((unsigned)nwg), dim3(GEMV_THREADS), 0, st, a, nrb);
   return hipGetLastError();
 }
 
 template <class S, class TA, class TI, class TO>
-static hipError_t adj_go(const GemvArgs& a, hipStream_t st) {
-  constexpr int RW = FTM_ADJ_RW, CPT = FTM_ADJ_CPT;
+static hipError_t fwd_go(const GemvArgs& a, hipStream_t st) {
+  switch (a.variant) {
+    case 1: return fwd_go_r<S, TA, TI, TO, 2>(a, st);
+    case 2: return fwd_go_r<S, TA, TI, TO, 8>(a, st);
+    default: return fwd_go_r<S, TA, TI, TO, FWD_ROWS>(a, st);
+  }
+}
+
+template <class S, class TA, class TI, class TO, int RW, int CPT>
+static hipError_t adj_go_l(const GemvArgs& a, hipStream_t st) {
   const int ncv = a.ld / S::V;
   const int per_wg = (GEMV_WAVES / RW) * 64 * CPT;
   const int nct = (ncv + per_wg - 1) / per_wg;
   const int64_t nwg = (int64_t)a.nrhs * a.K * nct;
   if (nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemv_adj_kernel<S, TA, TI, TO, RW, CPT>), dim3((unsigned)nwg), dim3(GEMV_THREADS), 0,
-                     st, a, nct);
+  hipLaunchKernelGGL((gemv_adj_kernel<S, TA, TI, TO, RW, CPT>), dim3((unsigned)nwg), dim3(GEMV_THREADS), 0, st, a,
+                     nct);
   return hipGetLastError();
+}
+
+template <class S, class TA, class TI, class TO>
+static hipError_t adj_go(const GemvArgs& a, hipStream_t st) {
+  switch (a.variant) {
+    case 1: return adj_go_l<S, TA, TI, TO, 2, 1>(a, st);
+    case 2: return adj_go_l<S, TA, TI, TO, 4, 2>(a, st);
+    default: return adj_go_l<S, TA, TI, TO, FTM_ADJ_RW, FTM_ADJ_CPT>(a, st);
+  }
 }
 
 // Supported (storage, accumulation, input, output) combinations: see the

@@ -71,7 +71,11 @@ struct GemvArgs {
   void* y;
   int64_t y_k_stride, y_rhs_stride;
   int r_gemv, r_next;
+  int variant;  // kernel variant (tile shape), 0 = default; see ftm_gemv.hip
 };
+
+// Number of tile-shape variants of the matrix-vector kernels.
+constexpr int GEMV_VARIANTS = 3;
 
 hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
                        const void* tw, hipStream_t st);

@@ -50,6 +50,8 @@ struct ftm_operator_s {
   ftm_precision fwd{}, adj{};
   int rhs_mode = FTM_RHS_AUTO;
   int64_t gemm_min_rhs = 2;
+  int variant[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // [direction][storage format] tile variant
+  double tuned_ms[2] = {0.0, 0.0};
 
   // instrumentation: events around the three kernels of each recorded call
   bool profiling = false;

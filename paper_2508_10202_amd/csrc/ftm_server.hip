@@ -156,6 +156,7 @@ static void on_batch_done(void* user) {
       srv->latency[r.ticket - 1] = t - r.t_submit;
       srv->state[r.ticket - 1] = ST_DONE;
     }
+    srv->stats.completed += s.reqs.size();  // counted when waiters are released
     srv->completed.push_back(c->index);
   }
   srv->cv_work.notify_one();
@@ -226,7 +227,6 @@ void ftm_server_s::run() {
       Slot& s = slots[idx];
       arena.release(s.ws_off, s.ws_bytes);
       inflight_requests -= (int64_t)s.reqs.size();
-      stats.completed += s.reqs.size();
       s.reqs.clear();
       s.busy = false;
     }

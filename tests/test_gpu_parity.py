@@ -341,3 +341,53 @@ def test_gemm_multi_rhs_shape(gpu):
         _say(f"  multi-rhs {prec}: fwd {e_f:.3e} [{lo_f:.1e},{hi_f:.1e}] adj {e_a:.3e} [{lo_a:.1e},{hi_a:.1e}]")
         assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
     op.close()
+
+
+# --- HIP graphs and the autotuner ------------------------------------------------------
+
+def test_graph_replays_match_eager(gpu):
+    """A captured matvec replayed several times, with eager work and
+    synchronisations in between: every replay equals the eager result."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(64, 16, 256)
+    F, m, d = make_F(s, 101), make_m(s, 102)[0], make_d(s, 103)[0]
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s",))
+    mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
+    for prec in ("ddddd", "dssdd"):
+        op.set_precision(fwd=prec, adj=prec)
+        ef, ea = op.matvec(mt).clone(), op.rmatvec(dt).clone()
+        gf, ga = op.graph(mt), op.graph(dt, adjoint=True)
+        for rep in range(4):
+            gf.y.zero_()
+            ga.y.zero_()
+            torch.cuda.synchronize()
+            gf.launch()
+            ga.launch()
+            op.matvec(mt)                       # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(gf.y[0], ef) and torch.equal(ga.y[0], ea), (prec, rep)
+        gf.close()
+        ga.close()
+    op.close()
+    assert _rel(ef.cpu().numpy(), oracle.forward(F, m)) <= 1e-6
+
+
+def test_autotune_keeps_results_and_caches(gpu, tmp_path):
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(100, 37, 1000)
+    F, m, d = make_F(s, 111), make_m(s, 112)[0], make_d(s, 113)[0]
+    op = Operator(torch.from_numpy(F).cuda())
+    cache = str(tmp_path / "tune.json")
+    rec = op.autotune(reps=3, cache=cache)
+    assert not rec["cached"] and 0 <= rec["fwd_variant"] < 3 and 0 <= rec["adj_variant"] < 3
+    assert rec["fwd_ms"] > 0 and rec["adj_ms"] > 0
+    assert op.autotune(cache=cache)["cached"]
+    mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
+    ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
+    for v in range(3):                          # every variant computes the same product
+        op.set_tuning(v, v)
+        assert _rel(op.matvec(mt).cpu().numpy(), ref_d) <= FP64_TOL
+        assert _rel(op.rmatvec(dt).cpu().numpy(), ref_m) <= FP64_TOL
+    op.close()

@@ -23,7 +23,7 @@ def ops():
     Fs = [make_F(s, 500 + i) for i, s in enumerate(shapes)]
     out = []
     for s, F in zip(shapes, Fs):
-        out.append((s, F, Operator(torch.from_numpy(F).cuda(), spectra=("s",))))
+        out.append((s, F, Operator(torch.from_numpy(F).cuda(), spectra=("s",), max_rhs=8)))
     yield out
     for _, _, op in out:
         op.close()
@@ -58,6 +58,14 @@ def test_mix_equals_alone(gpu, ops, prec):
     from paper_2508_10202_amd import Server
     for _, _, op in ops:
         op.set_precision(fwd=prec, adj=prec)
+    try:
+        _mix_equals_alone(ops, prec, Server, torch)
+    finally:
+        for _, _, op in ops:
+            op.set_precision(fwd="ddddd", adj="ddddd")
+
+
+def _mix_equals_alone(ops, prec, Server, torch):
     reqs = _requests(ops, 60, seed=1 if prec == "ddddd" else 2)
     xs = [torch.from_numpy(x).cuda() for _, _, x in reqs]
     torch.cuda.synchronize()
@@ -83,8 +91,6 @@ def test_mix_equals_alone(gpu, ops, prec):
             assert oracle.relative_l2(got, alone) <= tol
         n_bitwise += int(np.array_equal(got, alone))
     _say(f"  {n_bitwise}/{len(reqs)} bitwise equal to the lone run")
-    for _, _, op in ops:
-        op.set_precision(fwd="ddddd", adj="ddddd")
 
 
 def test_tiny_budget_queues_instead_of_failing(gpu, ops):
@@ -92,6 +98,8 @@ def test_tiny_budget_queues_instead_of_failing(gpu, ops):
     wait for workspace (budget_waits > 0), never fail, never exceed it."""
     import torch
     from paper_2508_10202_amd import Server
+    for _, _, op in ops:
+        op.set_precision(fwd="ddddd", adj="ddddd")
     need = max(_ws(op, 8) for _, _, op in ops)
     reqs = _requests(ops, 40, seed=3)
     xs = [torch.from_numpy(x).cuda() for _, _, x in reqs]
