@@ -88,7 +88,13 @@ bool make_plan(int N, FftPlan* plan) {
   if (n != 1 || (int)rad.size() > MAX_STAGES) return false;
   plan->N = N;
   plan->nst = (int)rad.size();
-  for (int i = 0; i < plan->nst; ++i) plan->rad[i] = rad[i];
+  int Ns = 1;
+  for (int i = 0; i < plan->nst; ++i) {
+    plan->rad[i] = rad[i];
+    plan->div_nb[i] = make_fastdiv((uint32_t)(N / rad[i]));
+    plan->div_ns[i] = make_fastdiv((uint32_t)Ns);
+    Ns *= rad[i];
+  }
   return true;
 }
 

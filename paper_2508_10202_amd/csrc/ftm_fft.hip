@@ -119,7 +119,7 @@ __device__ __forceinline__ void dft(cplx<T>* a) {
 // Ns is the product of the radices of the earlier passes.  All reads of the
 // pass complete (barrier) before any write, so the pass works in place.
 template <int R, int TH, int PTS, class T>
-__device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
+__device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns, FastDiv dnb, FastDiv dns,
                                          const cplx<T>* __restrict__ tw) {
   constexpr int MAXB = (PTS / TH + R - 1) / R;  // butterflies per thread
   const int nb = N / R;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
   for (int i = 0; i < MAXB; ++i) {
     const int b = threadIdx.x + i * TH;
     if (b < total) {
-      const int p = b / nb, j = b - p * nb, jm = j % Ns;
+      const int p = (int)fast_div(b, dnb), j = b - p * nb, jm = j - (int)fast_div(j, dns) * Ns;
       const cplx<T>* src = lds + p * N + j;
       v[i][0] = src[0];
 #pragma unroll
@@ -143,7 +143,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns,
     const int b = threadIdx.x + i * TH;
     if (b < total) {
       dft<R>(v[i]);
-      const int p = b / nb, j = b - p * nb, jm = j % Ns;
+      const int p = (int)fast_div(b, dnb), j = b - p * nb, jm = j - (int)fast_div(j, dns) * Ns;
       cplx<T>* dst = lds + p * N + (j - jm) * R + jm;
 #pragma unroll
       for (int q = 0; q < R; ++q) dst[q * Ns] = v[i][q];
@@ -161,14 +161,14 @@ __device__ void fft_lds(cplx<T>* lds, const FftPlan& plan, int P, const cplx<T>*
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.rad[s];
     switch (R) {
-      case 2: fft_pass<2, TH, PTS>(lds, plan.N, P, Ns, tw); break;
-      case 3: fft_pass<3, TH, PTS>(lds, plan.N, P, Ns, tw); break;
-      case 4: fft_pass<4, TH, PTS>(lds, plan.N, P, Ns, tw); break;
-      case 5: fft_pass<5, TH, PTS>(lds, plan.N, P, Ns, tw); break;
+      case 2: fft_pass<2, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
+      case 3: fft_pass<3, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
+      case 4: fft_pass<4, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
+      case 5: fft_pass<5, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
       case 7:
-        if constexpr (R7) fft_pass<7, TH, PTS>(lds, plan.N, P, Ns, tw);
+        if constexpr (R7) fft_pass<7, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw);
         break;
-      default: fft_pass<8, TH, PTS>(lds, plan.N, P, Ns, tw); break;
+      default: fft_pass<8, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
     }
     Ns *= R;
   }
@@ -188,16 +188,14 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
   cplx<TC>* lds = reinterpret_cast<cplx<TC>*>(smem_raw);
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t b = wg / npb, pb = wg - b * npb;
-  const int64_t s0 = pb * 2 * P;
   const int N = plan.N, Nt = a.Nt, two_p = 2 * P;
+  const int64_t s0 = pb * two_p;
+  const int lg = 31 - __clz(two_p);  // P is a power of two
   const int tid = threadIdx.x;
 
   // zero padding t = Nt .. N-1 (phase 1)
-  const int padlen = N - Nt;
-  for (int i = tid; i < P * padlen; i += TH) {
-    const int p = i / padlen, t = Nt + (i - p * padlen);
-    lds[p * N + t] = {(TC)0, (TC)0};
-  }
+  for (int p = 0; p < P; ++p)
+    for (int t = Nt + tid; t < N; t += TH) lds[p * N + t] = {(TC)0, (TC)0};
   // load, rounded to the pad and FFT formats; series 2p -> real, 2p+1 -> imaginary
   const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
   const int nload = Nt * two_p;
@@ -206,7 +204,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
 #pragma unroll
     for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
       const int i = base + u * TH;
-      const int t = i / two_p, j = i - t * two_p;
+      const int t = i >> lg, j = i & (two_p - 1);
       const int64_t s = s0 + j;
       v[u] = (i < nload && s < a.S) ? xb[(int64_t)t * a.x_row_stride + s] : 0.0;
     }
@@ -214,7 +212,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
       const int i = base + u * TH;
       if (i < nload) {
-        const int t = i / two_p, j = i - t * two_p;
+        const int t = i >> lg, j = i & (two_p - 1);
         TC* comp = reinterpret_cast<TC*>(lds + (j >> 1) * N + t);
         comp[j & 1] = (TC)round_to(round_to(v[u], a.r_pad), a.r_fft);
       }
@@ -228,8 +226,9 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
   // Y = (Z_k - conj Z_{N-k}) / 2i; keep bins 0 .. N/2
   const int K = N / 2 + 1;
   TO* outb = reinterpret_cast<TO*>(a.out);
+  const bool vec = a.ncol >= a.S;  // one output row per right-hand side (not the setup transform)
   for (int i = tid; i < K * two_p; i += TH) {
-    const int k = i / two_p, j = i - k * two_p;
+    const int k = i >> lg, j = i & (two_p - 1);
     const int64_t s = s0 + j;
     if (s >= a.S) continue;
     const cplx<TC>* z = lds + (j >> 1) * N;
@@ -238,7 +237,8 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     if ((j & 1) == 0) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
     else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
     X = round_to(round_to(X, a.r_fft), a.r_next);
-    const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + (s / a.ncol) * a.ld_row + s % a.ncol;
+    const int64_t row = vec ? 0 : s / a.ncol;
+    const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + row * a.ld_row + (s - row * a.ncol);
     reinterpret_cast<cplx<TO>*>(outb)[off] = {(TO)X.x, (TO)X.y};  // one 16/8-byte store
   }
   // the last pair block of a right-hand side also clears the padding columns
@@ -263,8 +263,9 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
   cplx<TC>* lds = reinterpret_cast<cplx<TC>*>(smem_raw);
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t b = wg / npb, pb = wg - b * npb;
-  const int64_t s0 = pb * 2 * P;
   const int N = plan.N, Nt = a.Nt, two_p = 2 * P, hN = N / 2;
+  const int64_t s0 = pb * two_p;
+  const int lgp = 31 - __clz(P), lg = lgp + 1;  // P is a power of two
   const int tid = threadIdx.x;
   const TI* inb = reinterpret_cast<const TI*>(a.in);
 
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
 #pragma unroll
     for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
       const int i = base + u * TH;
-      const int k = i / P, p = i - k * P;
+      const int k = i >> lgp, p = i & (P - 1);
       const int64_t s = s0 + 2 * p;
       const int64_t off = 2 * (k * a.in_k_stride + b * a.in_rhs_stride + s);
       A[u] = {(TC)0, (TC)0};
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
     for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
       const int i = base + u * TH;
       if (i >= nload) continue;
-      const int k = i / P, p = i - k * P;
+      const int k = i >> lgp, p = i & (P - 1);
       cplx<TC> Au = round_to(A[u], a.r_ifft), Bu = round_to(B[u], a.r_ifft);
       if (k == 0 || k == hN) {
         Au.y = (TC)0;
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
   const TC inv_n = (TC)(1.0 / (double)N);
   double* yb = a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride;
   for (int i = tid; i < Nt * two_p; i += TH) {
-    const int t = i / two_p, j = i - t * two_p;
+    const int t = i >> lg, j = i & (two_p - 1);
     const int64_t s = s0 + j;
     if (s >= a.S) continue;
     const cplx<TC> z = lds[(j >> 1) * N + t];  // conj of N * (a_t + i b_t)
@@ -323,10 +324,10 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
 // Complex series per workgroup: as many length-N series as fit in PTS points,
 // but no more pairs than there are series.
 static int pairs_per_wg(int N, int64_t S, int pts) {
-  int P = pts / N;
-  if (P < 1) P = 1;
+  // a power of two (index arithmetic by shifts), no more than fit or are needed
   const int64_t need = (S + 1) / 2;
-  if (need < P) P = (int)need;
+  int P = 1;
+  while (2 * P * N <= pts && 2 * P <= need) P *= 2;
   return P;
 }
 

@@ -20,11 +20,34 @@ constexpr int MAX_STAGES = 16;
 constexpr int FFT_POINTS = FTM_FFT_POINTS;
 constexpr int FFT_THREADS = FTM_FFT_THREADS;
 
+// Unsigned 32-bit division by an invariant divisor d via multiply-high
+// (Granlund and Montgomery, PLDI 1994, Fig. 4.1): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, n / d = (t + ((n - t) >> min(l,1))) >> max(l-1,0)
+// where t = mulhi(n, m), exact for every 32-bit n.
+struct FastDiv {
+  uint32_t m, s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 1 ? l - 1 : 0;
+  return f;
+}
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, FastDiv f) {
+  const uint32_t t = __umulhi(n, f.m);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 // Mixed-radix plan of a length-N complex FFT: N = rad[0] * rad[1] * ...
+// div_nb[s] divides by N / rad[s], div_ns[s] by rad[0] * .. * rad[s-1].
 struct FftPlan {
   int N;
   int nst;
   int rad[MAX_STAGES];
+  FastDiv div_nb[MAX_STAGES], div_ns[MAX_STAGES];
 };
 
 // Phases 1+2 (or the setup transform of F): real series x[b][t][s] (t < Nt,
