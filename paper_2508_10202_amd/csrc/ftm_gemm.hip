@@ -245,50 +245,69 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
 }
 
 // ---------------------------------------------------------------------------
-// adjoint, FP32 storage: MFMA 16x16x4 f32, reduction over r in steps of 4
+// adjoint: the reduction runs over sensors r in chunks of RC = 32.  Per chunk
+// the workgroup stages its spectrum tile Fhat_k[r0..r0+32)[c0..c0+64) and the
+// matching X_k[b0..b0+64)[r0..r0+32) through LDS with coalesced 16-byte rows;
+// the MFMA operands are then read from LDS.  Sensors past Nd are zero.
 // ---------------------------------------------------------------------------
-// X_k (nrhs x Nd complex) is read from global memory (it is small and shared
-// by every workgroup of the frequency, so it stays in cache).
+constexpr int RC = 32;
+
+// FP32 storage: MFMA 16x16x4 f32, 8 k-steps of 4 sensors per chunk.
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, int nbb, int ncb) {
+  __shared__ cplx<float> fs[RC][ADJ_BN + 2];
+  __shared__ cplx<float> xs[GEMM_BM][RC + 1];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * ncb;
   const int64_t k = wg / per_k;
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / ncb, cb = rem - bb * ncb;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN + w * 16;
-  const int c_me = min(c0 + l16, a.ld - 1);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN;
 
   const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
   const cplx<float>* __restrict__ Fk = reinterpret_cast<const cplx<float>*>(a.F) + k * a.f_k_stride;
-  int brow[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) brow[t] = min(b0 + 16 * t + l16, a.nrhs - 1);
 
   f32x4 re[4], im[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // sensors past Nd contribute zero; their spectrum row index is clamped
-  const int nr = (a.Nd + 3) / 4 * 4;
-#pragma unroll 2
-  for (int r0 = 0; r0 < nr; r0 += 4) {
-    const int r = r0 + g;
-    const int rf = min(r, a.Nd - 1);
-    const cplx<float> f = Fk[(int64_t)rf * a.ld + c_me];
-    cplx<float> x[4];
+  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
+    // spectrum tile: 32 rows x 64 columns, two complex per 16-byte load
 #pragma unroll
-    for (int t = 0; t < 4; ++t) x[t] = r < a.Nd ? X[(int64_t)brow[t] * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t].x, f.x, re[t], 0, 0, 0);
-      re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t].y, f.y, re[t], 0, 0, 0);
-      im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t].y, f.x, im[t], 0, 0, 0);
-      im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x[t].x, f.y, im[t], 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx >> 5, col = (idx & 31) * 2;
+      const int r = r0 + row, c = c0 + col;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < a.Nd && c < a.ld) v = __builtin_bit_cast(float4, load_stream(Fk + (int64_t)r * a.ld + c));
+      fs[row][col] = {v.x, v.y};
+      fs[row][col + 1] = {v.z, v.w};
     }
+    // data tile: 64 right-hand sides x 32 sensors
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int bl = idx >> 5, rr = idx & 31;
+      const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
+      xs[bl][rr] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < RC / 4; ++s) {
+      const cplx<float> f = fs[4 * s + g][w * 16 + l16];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const cplx<float> x = xs[16 * t + l16][4 * s + g];
+        re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, f.x, re[t], 0, 0, 0);
+        re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, f.y, re[t], 0, 0, 0);
+        im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, f.x, im[t], 0, 0, 0);
+        im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-x.x, f.y, im[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
 
-  const int c = c0 + l16;
+  const int c = c0 + w * 16 + l16;
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
 #pragma unroll
@@ -296,87 +315,87 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) {
-        float* y = Y + 2 * (b * a.y_rhs_stride + c);
-        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
-      }
+      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
     }
 }
 
-// adjoint, FP16/BF16 storage: MFMA 16x16x32, 32 sensors per step.
-// Lane l16 + 16 g gathers its 8 k-values (sensors 8 g .. 8 g + 7) of one
-// column from 8 spectrum rows.
+// FP16/BF16 storage: MFMA 16x16x32, one k-step of 32 sensors per chunk.
 template <class S>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, int nbb, int ncb) {
   using M = MfmaOf<S>;
   using H = typename M::half_t;
+  __shared__ uint32_t fs[RC][ADJ_BN + 4];            // (re | im << 16) per complex
+  __shared__ __align__(16) uint16_t xr16[GEMM_BM][RC + 8];
+  __shared__ __align__(16) uint16_t xi16[GEMM_BM][RC + 8];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * ncb;
   const int64_t k = wg / per_k;
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / ncb, cb = rem - bb * ncb;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN + w * 16;
-  const int c_me = min(c0 + l16, a.ld - 1);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN;
 
   const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
   const uint32_t* __restrict__ Fk = reinterpret_cast<const uint32_t*>(a.F) + k * a.f_k_stride;
-  int brow[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) brow[t] = min(b0 + 16 * t + l16, a.nrhs - 1);
 
   f32x4 re[4], im[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  const int nr = (a.Nd + 31) / 32 * 32;
-  for (int r0 = 0; r0 < nr; r0 += 32) {
-    // B operands: fr and fi of sensors r0 + 8 g + u at column c_me
-    uint32_t fw[8];
+  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
+    // spectrum tile: 32 rows x 64 columns, four complex per 16-byte load
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = r0 + 8 * g + u;
-      fw[u] = r < a.Nd ? Fk[(int64_t)r * a.ld + c_me] : 0u;
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx >> 4, col = (idx & 15) * 4;
+      const int r = r0 + row, c = c0 + col;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (r < a.Nd && c < a.ld) v = load_stream(Fk + (int64_t)r * a.ld + c);
+      fs[row][col] = v.x;
+      fs[row][col + 1] = v.y;
+      fs[row][col + 2] = v.z;
+      fs[row][col + 3] = v.w;
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int bl = idx >> 5, rr = idx & 31;
+      const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
+      const cplx<float> x = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+      xr16[bl][rr] = (uint16_t)to_bits16<H>(x.x);  // exact: x holds values of the 16-bit format
+      xi16[bl][rr] = (uint16_t)to_bits16<H>(x.y);
+    }
+    __syncthreads();
+    // B operands: fr and fi of sensors 8 g .. 8 g + 7 at this lane's column
     uint4 ufr, ufi;
     uint32_t* pr = reinterpret_cast<uint32_t*>(&ufr);
     uint32_t* pi = reinterpret_cast<uint32_t*>(&ufi);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      pr[q] = (fw[2 * q] & 0xffffu) | (fw[2 * q + 1] << 16);
-      pi[q] = (fw[2 * q] >> 16) | (fw[2 * q + 1] & 0xffff0000u);
+      const uint32_t w0 = fs[8 * g + 2 * q][w * 16 + l16], w1 = fs[8 * g + 2 * q + 1][w * 16 + l16];
+      pr[q] = (w0 & 0xffffu) | (w1 << 16);
+      pi[q] = (w0 >> 16) | (w1 & 0xffff0000u);
     }
-    const typename M::vec fr = *reinterpret_cast<const typename M::vec*>(&ufr);
-    const typename M::vec fi = *reinterpret_cast<const typename M::vec*>(&ufi);
+    const typename M::vec fr = __builtin_bit_cast(typename M::vec, ufr);
+    const typename M::vec fi = __builtin_bit_cast(typename M::vec, ufi);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      // A operands: x of right-hand side brow[t] at the same 8 sensors
-      uint4 uxr, uxi, uxn;
-      uint32_t* qr = reinterpret_cast<uint32_t*>(&uxr);
-      uint32_t* qi = reinterpret_cast<uint32_t*>(&uxi);
-      uint32_t* qn = reinterpret_cast<uint32_t*>(&uxn);
-      const cplx<float>* xr = X + (int64_t)brow[t] * a.x_rhs_stride;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        // sensors past Nd contribute zero
-        const int r = r0 + 8 * g + 2 * q;
-        const cplx<float> z = {0.f, 0.f};
-        const cplx<float> x0 = r < a.Nd ? xr[r] : z, x1 = r + 1 < a.Nd ? xr[r + 1] : z;
-        qr[q] = to_bits16<H>(x0.x) | (to_bits16<H>(x1.x) << 16);
-        qi[q] = to_bits16<H>(x0.y) | (to_bits16<H>(x1.y) << 16);
-        qn[q] = qr[q] ^ 0x80008000u;
-      }
-      const typename M::vec vxr = *reinterpret_cast<const typename M::vec*>(&uxr);
-      const typename M::vec vxi = *reinterpret_cast<const typename M::vec*>(&uxi);
-      const typename M::vec vxn = *reinterpret_cast<const typename M::vec*>(&uxn);
+      const uint4 uxr = *reinterpret_cast<const uint4*>(&xr16[16 * t + l16][8 * g]);
+      const uint4 uxi = *reinterpret_cast<const uint4*>(&xi16[16 * t + l16][8 * g]);
+      const uint4 uxn = make_uint4(uxr.x ^ 0x80008000u, uxr.y ^ 0x80008000u, uxr.z ^ 0x80008000u,
+                                   uxr.w ^ 0x80008000u);
+      const typename M::vec vxr = __builtin_bit_cast(typename M::vec, uxr);
+      const typename M::vec vxi = __builtin_bit_cast(typename M::vec, uxi);
+      const typename M::vec vxn = __builtin_bit_cast(typename M::vec, uxn);
       re[t] = M::mma(vxr, fr, re[t]);
       re[t] = M::mma(vxi, fi, re[t]);
       im[t] = M::mma(vxi, fr, im[t]);
       im[t] = M::mma(vxn, fi, im[t]);
     }
+    __syncthreads();
   }
 
-  const int c = c0 + l16;
+  const int c = c0 + w * 16 + l16;
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
 #pragma unroll
@@ -384,10 +403,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) {
-        float* y = Y + 2 * (b * a.y_rhs_stride + c);
-        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
-      }
+      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
     }
 }
 
