@@ -15,6 +15,39 @@
 
 namespace ftm {
 
+// ---- LDS layout ------------------------------------------------------------------
+// Complex element i of the workgroup's LDS arrays lives at slot lds_ix(i).  The
+// early Stockham passes write with strides of R and of R * Ns elements, which
+// hit the same LDS banks from many lanes; the remap spreads them.
+//   0: identity   1: one pad element per 8   2: one pad element per 16
+//   3: XOR of the 16-element slot with the row index (no extra space)
+#ifndef FTM_LDS_SWIZZLE
+#define FTM_LDS_SWIZZLE 3
+#endif
+__device__ __forceinline__ int lds_ix(int i) {
+#if FTM_LDS_SWIZZLE == 1
+  return i + (i >> 3);
+#elif FTM_LDS_SWIZZLE == 2
+  return i + (i >> 4);
+#elif FTM_LDS_SWIZZLE == 3
+  return i ^ ((i >> 4) & 15);
+#else
+  return i;
+#endif
+}
+// LDS elements needed for n logical elements
+__host__ __device__ constexpr int lds_size(int n) {
+#if FTM_LDS_SWIZZLE == 1
+  return n + (n >> 3) + 1;
+#elif FTM_LDS_SWIZZLE == 2
+  return n + (n >> 4) + 1;
+#elif FTM_LDS_SWIZZLE == 3
+  return (n + 15) / 16 * 16;
+#else
+  return n;
+#endif
+}
+
 // ---- R-point DFTs, forward sign exp(-2 pi i jk / R) --------------------------
 
 template <class T>
@@ -131,10 +164,10 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns, Fas
     const int b = threadIdx.x + i * TH;
     if (b < total) {
       const int p = (int)fast_div(b, dnb), j = b - p * nb, jm = j - (int)fast_div(j, dns) * Ns;
-      const cplx<T>* src = lds + p * N + j;
-      v[i][0] = src[0];
+      const int src = p * N + j;
+      v[i][0] = lds[lds_ix(src)];
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i][q] = cmul(src[q * nb], tw[q * jm * tstride]);
+      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(src + q * nb)], tw[q * jm * tstride]);
     }
   }
   __syncthreads();
@@ -144,9 +177,9 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns, Fas
     if (b < total) {
       dft<R>(v[i]);
       const int p = (int)fast_div(b, dnb), j = b - p * nb, jm = j - (int)fast_div(j, dns) * Ns;
-      cplx<T>* dst = lds + p * N + (j - jm) * R + jm;
+      const int dst = p * N + (j - jm) * R + jm;
 #pragma unroll
-      for (int q = 0; q < R; ++q) dst[q * Ns] = v[i][q];
+      for (int q = 0; q < R; ++q) lds[lds_ix(dst + q * Ns)] = v[i][q];
     }
   }
   __syncthreads();
@@ -195,7 +228,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
 
   // zero padding t = Nt .. N-1 (phase 1)
   for (int p = 0; p < P; ++p)
-    for (int t = Nt + tid; t < N; t += TH) lds[p * N + t] = {(TC)0, (TC)0};
+    for (int t = Nt + tid; t < N; t += TH) lds[lds_ix(p * N + t)] = {(TC)0, (TC)0};
   // load, rounded to the pad and FFT formats; series 2p -> real, 2p+1 -> imaginary
   const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
   const int nload = Nt * two_p;
@@ -213,7 +246,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
       const int i = base + u * TH;
       if (i < nload) {
         const int t = i >> lg, j = i & (two_p - 1);
-        TC* comp = reinterpret_cast<TC*>(lds + (j >> 1) * N + t);
+        TC* comp = reinterpret_cast<TC*>(lds + lds_ix((j >> 1) * N + t));
         comp[j & 1] = (TC)round_to(round_to(v[u], a.r_pad), a.r_fft);
       }
     }
@@ -231,8 +264,8 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     const int k = i >> lg, j = i & (two_p - 1);
     const int64_t s = s0 + j;
     if (s >= a.S) continue;
-    const cplx<TC>* z = lds + (j >> 1) * N;
-    const cplx<TC> zk = z[k], zr = z[k == 0 ? 0 : N - k];
+    const int zb = (j >> 1) * N;
+    const cplx<TC> zk = lds[lds_ix(zb + k)], zr = lds[lds_ix(zb + (k == 0 ? 0 : N - k))];
     cplx<TC> X;
     if ((j & 1) == 0) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
     else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
@@ -298,8 +331,8 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
         Au.y = (TC)0;
         Bu.y = (TC)0;
       }
-      lds[p * N + k] = {Au.x - Bu.y, -(Au.y + Bu.x)};
-      if (k > 0 && k < hN) lds[p * N + N - k] = {Au.x + Bu.y, Au.y - Bu.x};
+      lds[lds_ix(p * N + k)] = {Au.x - Bu.y, -(Au.y + Bu.x)};
+      if (k > 0 && k < hN) lds[lds_ix(p * N + N - k)] = {Au.x + Bu.y, Au.y - Bu.x};
     }
   }
   __syncthreads();
@@ -312,7 +345,7 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
     const int t = i >> lg, j = i & (two_p - 1);
     const int64_t s = s0 + j;
     if (s >= a.S) continue;
-    const cplx<TC> z = lds[(j >> 1) * N + t];  // conj of N * (a_t + i b_t)
+    const cplx<TC> z = lds[lds_ix((j >> 1) * N + t)];  // conj of N * (a_t + i b_t)
     TC v = ((j & 1) == 0 ? z.x : -z.y) * inv_n;
     v = round_to(v, a.r_ifft);
     yb[(int64_t)t * a.y_row_stride + s] = round_to((double)v, a.r_unpad);
@@ -355,7 +388,7 @@ static hipError_t rfft_go_shape(const RfftArgs& a, const FftPlan& plan, const vo
   const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
   const int64_t nwg = npb * a.nrhs;
   if (nwg <= 0) return hipSuccess;
-  const size_t lds = (size_t)P * plan.N * sizeof(cplx<TC>);
+  const size_t lds = (size_t)lds_size(P * plan.N) * sizeof(cplx<TC>);
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
   if (plan_has7(plan))
     hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st, a,
@@ -384,7 +417,7 @@ static hipError_t irfft_go_shape(const IrfftArgs& a, const FftPlan& plan, const 
   const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
   const int64_t nwg = npb * a.nrhs;
   if (nwg <= 0) return hipSuccess;
-  const size_t lds = (size_t)P * plan.N * sizeof(cplx<TC>);
+  const size_t lds = (size_t)lds_size(P * plan.N) * sizeof(cplx<TC>);
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
   if (plan_has7(plan))
     hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st,
