@@ -39,27 +39,20 @@ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y
 // implicit bit included), smallest normal exponent emin and largest finite
 // value maxv.  Values below the normal range are rounded on the subnormal
 // grid 2^(emin-p+1); values that round beyond maxv become infinities.  The
-// scaling by the quantum q is exact (q is a power of two and x/q stays well
-// inside the double range), and rint rounds half-way cases to even.
+// scalings by powers of two are exact (x is brought to at most p integer
+// bits and back), and rint rounds half-way cases to even.
 __device__ __forceinline__ double round_fmt(double x, int p, int emin, double maxv) {
-  const double ax = fabs(x);
-  if (!(ax > 0.0) || isinf(ax)) return x;
-  int e = ilogb(ax);
-  if (e < emin) e = emin;
-  const double q = ldexp(1.0, e - p + 1);
-  double r = rint(x / q) * q;
-  if (fabs(r) > maxv) r = copysign(__builtin_inf(), x);
-  return r;
+  // exponent of x (0 and non-finite x give -1; both pass through unchanged)
+  int e = __builtin_amdgcn_frexp_exp(x) - 1;
+  e = e < emin ? emin : e;
+  const double r = ldexp(rint(ldexp(x, p - 1 - e)), e - p + 1);
+  return fabs(r) > maxv ? copysign(__builtin_inf(), x) : r;
 }
 __device__ __forceinline__ float round_fmt(float x, int p, int emin, float maxv) {
-  const float ax = fabsf(x);
-  if (!(ax > 0.0f) || isinf(ax)) return x;
-  int e = ilogbf(ax);
-  if (e < emin) e = emin;
-  const float q = ldexpf(1.0f, e - p + 1);
-  float r = rintf(x / q) * q;
-  if (fabsf(r) > maxv) r = copysignf(__builtin_inff(), x);
-  return r;
+  int e = __builtin_amdgcn_frexp_expf(x) - 1;
+  e = e < emin ? emin : e;
+  const float r = ldexpf(rintf(ldexpf(x, p - 1 - e)), e - p + 1);
+  return fabsf(r) > maxv ? copysignf(__builtin_inff(), x) : r;
 }
 
 constexpr double F16_MAX = 65504.0;
@@ -84,6 +77,24 @@ __device__ __forceinline__ float round_to(float x, int dt) {
 template <class T>
 __device__ __forceinline__ cplx<T> round_to(cplx<T> a, int dt) {
   return {round_to(a.x, dt), round_to(a.y, dt)};
+}
+
+// round_to for kernels that know at compile time whether any format they apply
+// is a half format (HALF); without one the rounding is a select (float64
+// values into float32) or nothing (float32 values), with no branches.
+template <bool HALF>
+__device__ __forceinline__ double round_as(double x, int dt) {
+  if constexpr (HALF) return round_to(x, dt);
+  else return dt == DT_F32 ? (double)(float)x : x;
+}
+template <bool HALF>
+__device__ __forceinline__ float round_as(float x, int dt) {
+  if constexpr (HALF) return round_to(x, dt);
+  else return x;
+}
+template <bool HALF, class T>
+__device__ __forceinline__ cplx<T> round_as(cplx<T> a, int dt) {
+  return {round_as<HALF>(a.x, dt), round_as<HALF>(a.y, dt)};
 }
 
 // ---------------------------------------------------------------------------

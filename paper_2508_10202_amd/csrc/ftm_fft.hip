@@ -213,7 +213,11 @@ __device__ void fft_lds(cplx<T>* lds, const FftPlan& plan, int P, const cplx<T>*
 // parallelism for the strided time-series reads).
 constexpr int FFT_LOAD_BATCH = 4;
 
-template <class TC, class TO, bool R7, int TH, int PTS>
+// Every thread keeps one column (series) of its pair block for the loads and
+// the stores, so its addresses advance by a fixed stride: thread tid owns
+// column tid mod 2P and rows (or bins) tid / 2P, tid / 2P + TH / 2P, ...
+
+template <class TC, class TO, bool R7, bool HALF, int TH, int PTS>
 __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
                                                                const cplx<TC>* __restrict__ tw,
                                                                int P, int64_t npb) {
@@ -223,32 +227,31 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
   const int64_t b = wg / npb, pb = wg - b * npb;
   const int N = plan.N, Nt = a.Nt, two_p = 2 * P;
   const int64_t s0 = pb * two_p;
-  const int lg = 31 - __clz(two_p);  // P is a power of two
+  const int lg = 31 - __clz(two_p);  // P is a power of two, 2P <= TH
   const int tid = threadIdx.x;
+  const int j = tid & (two_p - 1), r0 = tid >> lg, rstep = TH >> lg;
+  const int64_t s = s0 + j;
+  const bool live = s < a.S;
 
   // zero padding t = Nt .. N-1 (phase 1)
   for (int p = 0; p < P; ++p)
     for (int t = Nt + tid; t < N; t += TH) lds[lds_ix(p * N + t)] = {(TC)0, (TC)0};
   // load, rounded to the pad and FFT formats; series 2p -> real, 2p+1 -> imaginary
-  const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
-  const int nload = Nt * two_p;
-  for (int base = tid; base < nload; base += FFT_LOAD_BATCH * TH) {
-    double v[FFT_LOAD_BATCH];
+  {
+    const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
+    const double* xs = xb + (live ? s : 0);
+    const int64_t xstep = (int64_t)rstep * a.x_row_stride;
+    TC* comp = reinterpret_cast<TC*>(lds) + (j & 1);
+    const int zb = (j >> 1) * N;
+    for (int t = r0; t < Nt; t += FFT_LOAD_BATCH * rstep) {
+      const double* q = xs + (int64_t)t * a.x_row_stride;
+      double v[FFT_LOAD_BATCH];
 #pragma unroll
-    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
-      const int i = base + u * TH;
-      const int t = i >> lg, j = i & (two_p - 1);
-      const int64_t s = s0 + j;
-      v[u] = (i < nload && s < a.S) ? xb[(int64_t)t * a.x_row_stride + s] : 0.0;
-    }
+      for (int u = 0; u < FFT_LOAD_BATCH; ++u) v[u] = (live && t + u * rstep < Nt) ? q[u * xstep] : 0.0;
 #pragma unroll
-    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
-      const int i = base + u * TH;
-      if (i < nload) {
-        const int t = i >> lg, j = i & (two_p - 1);
-        TC* comp = reinterpret_cast<TC*>(lds + lds_ix((j >> 1) * N + t));
-        comp[j & 1] = (TC)round_to(round_to(v[u], a.r_pad), a.r_fft);
-      }
+      for (int u = 0; u < FFT_LOAD_BATCH; ++u)
+        if (t + u * rstep < Nt)
+          comp[2 * lds_ix(zb + t + u * rstep)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), a.r_fft);
     }
   }
   __syncthreads();
@@ -258,37 +261,39 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
   // separate the two real spectra: X = (Z_k + conj Z_{N-k}) / 2,
   // Y = (Z_k - conj Z_{N-k}) / 2i; keep bins 0 .. N/2
   const int K = N / 2 + 1;
-  TO* outb = reinterpret_cast<TO*>(a.out);
-  const bool vec = a.ncol >= a.S;  // one output row per right-hand side (not the setup transform)
-  for (int i = tid; i < K * two_p; i += TH) {
-    const int k = i >> lg, j = i & (two_p - 1);
-    const int64_t s = s0 + j;
-    if (s >= a.S) continue;
+  if (live) {
+    // one output row per right-hand side, or (the setup transform) the
+    // columns s of row s / ncol of a [Nd][ld_row] block per bin
+    const int64_t row = a.ncol >= a.S ? 0 : s / a.ncol;
+    cplx<TO>* o = reinterpret_cast<cplx<TO>*>(a.out) + b * a.out_rhs_stride + row * a.ld_row + (s - row * a.ncol) +
+                  r0 * a.out_k_stride;
+    const int64_t ostep = (int64_t)rstep * a.out_k_stride;
     const int zb = (j >> 1) * N;
-    const cplx<TC> zk = lds[lds_ix(zb + k)], zr = lds[lds_ix(zb + (k == 0 ? 0 : N - k))];
-    cplx<TC> X;
-    if ((j & 1) == 0) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
-    else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
-    X = round_to(round_to(X, a.r_fft), a.r_next);
-    const int64_t row = vec ? 0 : s / a.ncol;
-    const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + row * a.ld_row + (s - row * a.ncol);
-    reinterpret_cast<cplx<TO>*>(outb)[off] = {(TO)X.x, (TO)X.y};  // one 16/8-byte store
+    const bool odd = j & 1;
+    for (int k = r0; k < K; k += rstep, o += ostep) {
+      const cplx<TC> zk = lds[lds_ix(zb + k)], zr = lds[lds_ix(zb + (k == 0 ? 0 : N - k))];
+      cplx<TC> X;
+      if (!odd) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
+      else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
+      X = round_as<HALF>(round_as<HALF>(X, a.r_fft), a.r_next);
+      *o = {(TO)X.x, (TO)X.y};  // one 16/8-byte store
+    }
   }
   // the last pair block of a right-hand side also clears the padding columns
   // (the products read them, multiplied by the spectrum's zero padding)
   if (pb == npb - 1 && a.pad_to > a.S) {
     const int npad = (int)(a.pad_to - a.S);
+    cplx<TO>* outb = reinterpret_cast<cplx<TO>*>(a.out);
     for (int i = tid; i < K * npad; i += TH) {
       const int k = i / npad;
-      const int64_t off = k * a.out_k_stride + b * a.out_rhs_stride + a.S + (i - k * npad);
-      reinterpret_cast<cplx<TO>*>(outb)[off] = {(TO)0, (TO)0};
+      outb[k * a.out_k_stride + b * a.out_rhs_stride + a.S + (i - k * npad)] = {(TO)0, (TO)0};
     }
   }
 }
 
 // ---- phases 4+5: inverse real FFT + scale + unpad ---------------------------
 
-template <class TI, class TC, bool R7, int TH, int PTS>
+template <class TI, class TC, bool R7, bool HALF, int TH, int PTS>
 __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan plan,
                                                                   const cplx<TC>* __restrict__ tw,
                                                                   int P, int64_t npb) {
@@ -298,57 +303,70 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
   const int64_t b = wg / npb, pb = wg - b * npb;
   const int N = plan.N, Nt = a.Nt, two_p = 2 * P, hN = N / 2;
   const int64_t s0 = pb * two_p;
-  const int lgp = 31 - __clz(P), lg = lgp + 1;  // P is a power of two
+  const int lgp = 31 - __clz(P), lg = lgp + 1;  // P is a power of two, 2P <= TH
   const int tid = threadIdx.x;
-  const TI* inb = reinterpret_cast<const TI*>(a.in);
 
   // Z = A + iB over the full length from the two half spectra (Hermitian
   // extension; the imaginary parts of bins 0 and N/2 are dropped, as a real
   // inverse transform does).  LDS receives conj(Z): the inverse transform is
-  // conj(FFT(conj Z)).
-  const int K = hN + 1;
-  const int nload = K * P;
-  for (int base = tid; base < nload; base += FFT_LOAD_BATCH * TH) {
-    cplx<TC> A[FFT_LOAD_BATCH], B[FFT_LOAD_BATCH];
+  // conj(FFT(conj Z)).  Thread tid reads pair tid mod P at bins tid / P + n TH / P.
+  {
+    const int K = hN + 1;
+    const int p = tid & (P - 1), k0 = tid >> lgp, kstep = TH >> lgp;
+    const int64_t s = s0 + 2 * p;
+    const bool liveA = s < a.S, liveB = s + 1 < a.S;
+    const cplx<TI>* in = reinterpret_cast<const cplx<TI>*>(a.in) + b * a.in_rhs_stride + (liveA ? s : 0);
+    const int64_t istep = (int64_t)kstep * a.in_k_stride;
+    const int pb_n = p * N;
+    for (int k = k0; k < K; k += FFT_LOAD_BATCH * kstep) {
+      const cplx<TI>* q = in + (int64_t)k * a.in_k_stride;
+      cplx<TC> A[FFT_LOAD_BATCH], B[FFT_LOAD_BATCH];
 #pragma unroll
-    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
-      const int i = base + u * TH;
-      const int k = i >> lgp, p = i & (P - 1);
-      const int64_t s = s0 + 2 * p;
-      const int64_t off = 2 * (k * a.in_k_stride + b * a.in_rhs_stride + s);
-      A[u] = {(TC)0, (TC)0};
-      B[u] = {(TC)0, (TC)0};
-      if (i < nload && s < a.S) A[u] = {(TC)inb[off], (TC)inb[off + 1]};
-      if (i < nload && s + 1 < a.S) B[u] = {(TC)inb[off + 2], (TC)inb[off + 3]};
-    }
-#pragma unroll
-    for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
-      const int i = base + u * TH;
-      if (i >= nload) continue;
-      const int k = i >> lgp, p = i & (P - 1);
-      cplx<TC> Au = round_to(A[u], a.r_ifft), Bu = round_to(B[u], a.r_ifft);
-      if (k == 0 || k == hN) {
-        Au.y = (TC)0;
-        Bu.y = (TC)0;
+      for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
+        A[u] = {(TC)0, (TC)0};
+        B[u] = {(TC)0, (TC)0};
+        if (k + u * kstep < K) {
+          if (liveA) {
+            const cplx<TI> v = q[u * istep];
+            A[u] = {(TC)v.x, (TC)v.y};
+          }
+          if (liveB) {
+            const cplx<TI> v = q[u * istep + 1];
+            B[u] = {(TC)v.x, (TC)v.y};
+          }
+        }
       }
-      lds[lds_ix(p * N + k)] = {Au.x - Bu.y, -(Au.y + Bu.x)};
-      if (k > 0 && k < hN) lds[lds_ix(p * N + N - k)] = {Au.x + Bu.y, Au.y - Bu.x};
+#pragma unroll
+      for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
+        const int kk = k + u * kstep;
+        if (kk >= K) continue;
+        cplx<TC> Au = round_as<HALF>(A[u], a.r_ifft), Bu = round_as<HALF>(B[u], a.r_ifft);
+        if (kk == 0 || kk == hN) {
+          Au.y = (TC)0;
+          Bu.y = (TC)0;
+        }
+        lds[lds_ix(pb_n + kk)] = {Au.x - Bu.y, -(Au.y + Bu.x)};
+        if (kk > 0 && kk < hN) lds[lds_ix(pb_n + N - kk)] = {Au.x + Bu.y, Au.y - Bu.x};
+      }
     }
   }
   __syncthreads();
 
   fft_lds<TC, R7, TH, PTS>(lds, plan, P, tw);
 
+  const int j = tid & (two_p - 1), t0 = tid >> lg, tstep = TH >> lg;
+  const int64_t s = s0 + j;
+  if (s >= a.S) return;
   const TC inv_n = (TC)(1.0 / (double)N);
-  double* yb = a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride;
-  for (int i = tid; i < Nt * two_p; i += TH) {
-    const int t = i >> lg, j = i & (two_p - 1);
-    const int64_t s = s0 + j;
-    if (s >= a.S) continue;
-    const cplx<TC> z = lds[lds_ix((j >> 1) * N + t)];  // conj of N * (a_t + i b_t)
-    TC v = ((j & 1) == 0 ? z.x : -z.y) * inv_n;
-    v = round_to(v, a.r_ifft);
-    yb[(int64_t)t * a.y_row_stride + s] = round_to((double)v, a.r_unpad);
+  double* y = (a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride) + s + (int64_t)t0 * a.y_row_stride;
+  const int64_t ystep = (int64_t)tstep * a.y_row_stride;
+  const int zb = (j >> 1) * N;
+  const bool odd = j & 1;
+  for (int t = t0; t < Nt; t += tstep, y += ystep) {
+    const cplx<TC> z = lds[lds_ix(zb + t)];  // conj of N * (a_t + i b_t)
+    TC v = (odd ? -z.y : z.x) * inv_n;
+    v = round_as<HALF>(v, a.r_ifft);
+    *y = round_as<HALF>((double)v, a.r_unpad);
   }
 }
 
@@ -356,13 +374,16 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
 
 // Complex series per workgroup: as many length-N series as fit in PTS points,
 // but no more pairs than there are series.
-static int pairs_per_wg(int N, int64_t S, int pts) {
-  // a power of two (index arithmetic by shifts), no more than fit or are needed
+static int pairs_per_wg(int N, int64_t S, int pts, int threads) {
+  // a power of two (index arithmetic by shifts), no more than fit or are
+  // needed, and at most one column per thread (2P <= threads)
   const int64_t need = (S + 1) / 2;
   int P = 1;
-  while (2 * P * N <= pts && 2 * P <= need) P *= 2;
+  while (2 * P * N <= pts && 2 * P <= need && 4 * P <= threads) P *= 2;
   return P;
 }
+
+static bool is_half(int dt) { return dt == DT_F16 || dt == DT_BF16; }
 
 static bool plan_has7(const FftPlan& plan) {
   for (int i = 0; i < plan.nst; ++i)
@@ -370,39 +391,57 @@ static bool plan_has7(const FftPlan& plan) {
   return false;
 }
 
-// Workgroup shapes: 512 threads over at most 2048 points (one butterfly per
-// thread for radices >= 4, 32 KiB of float64 LDS) up to N = 2048, else over
-// 4096 points.
+// Workgroup shapes.  float64: 512 threads over at most 2048 points (one
+// butterfly per thread for radices >= 4, 32 KiB of LDS) up to N = 2048, else
+// over 4096 points.  float32 takes more pairs per workgroup for the same LDS,
+// so that a workgroup reads and writes longer runs of adjacent columns.
 #ifndef FTM_FFT_TH
 #define FTM_FFT_TH 512
 #endif
 #ifndef FTM_FFT_SMALL_PTS
 #define FTM_FFT_SMALL_PTS 2048
 #endif
-constexpr int FFT_TH = FTM_FFT_TH;
-constexpr int FFT_SMALL_PTS = FTM_FFT_SMALL_PTS;
+#ifndef FTM_FFT_F32_TH
+#define FTM_FFT_F32_TH 512
+#endif
+#ifndef FTM_FFT_F32_SMALL_PTS
+#define FTM_FFT_F32_SMALL_PTS 2048
+#endif
+#ifndef FTM_FFT_F32_PTS
+#define FTM_FFT_F32_PTS 4096
+#endif
+static_assert(FTM_FFT_F32_PTS >= FFT_POINTS, "the float32 shape must hold the longest transform");
 
-template <class TC, class TO, int PTS>
+template <class TC, class TO, int PTS, int TH>
 static hipError_t rfft_go_shape(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  const int P = pairs_per_wg(plan.N, a.S, PTS);
+  const int P = pairs_per_wg(plan.N, a.S, PTS, TH);
   const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
   const int64_t nwg = npb * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   const size_t lds = (size_t)lds_size(P * plan.N) * sizeof(cplx<TC>);
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
-  if (plan_has7(plan))
-    hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st, a,
-                       plan, t, P, npb);
-  else
-    hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, false, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st, a,
-                       plan, t, P, npb);
+  const bool half = is_half(a.r_pad) || is_half(a.r_fft) || is_half(a.r_next);
+  const dim3 g((unsigned)nwg), blk(TH);
+  if (plan_has7(plan)) {
+    if (half) hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+    else hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+  } else {
+    if (half) hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, false, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+    else hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, false, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+  }
   return hipGetLastError();
 }
 
 template <class TC, class TO>
 static hipError_t rfft_go(const RfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  if (plan.N <= FFT_SMALL_PTS) return rfft_go_shape<TC, TO, FFT_SMALL_PTS>(a, plan, tw, st);
-  return rfft_go_shape<TC, TO, FFT_POINTS>(a, plan, tw, st);
+  if constexpr (sizeof(TC) == 4) {
+    if (plan.N <= FTM_FFT_F32_SMALL_PTS)
+      return rfft_go_shape<TC, TO, FTM_FFT_F32_SMALL_PTS, FTM_FFT_F32_TH>(a, plan, tw, st);
+    return rfft_go_shape<TC, TO, FTM_FFT_F32_PTS, FTM_FFT_F32_TH>(a, plan, tw, st);
+  } else {
+    if (plan.N <= FTM_FFT_SMALL_PTS) return rfft_go_shape<TC, TO, FTM_FFT_SMALL_PTS, FTM_FFT_TH>(a, plan, tw, st);
+    return rfft_go_shape<TC, TO, FFT_POINTS, FTM_FFT_TH>(a, plan, tw, st);
+  }
 }
 
 hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan, const void* tw,
@@ -411,27 +450,40 @@ hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& 
   return rfft_go<float, float>(a, plan, tw, st);
 }
 
-template <class TI, class TC, int PTS>
+template <class TI, class TC, int PTS, int TH>
 static hipError_t irfft_go_shape(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  const int P = pairs_per_wg(plan.N, a.S, PTS);
+  const int P = pairs_per_wg(plan.N, a.S, PTS, TH);
   const int64_t npb = (a.S + 2 * P - 1) / (2 * P);
   const int64_t nwg = npb * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   const size_t lds = (size_t)lds_size(P * plan.N) * sizeof(cplx<TC>);
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
-  if (plan_has7(plan))
-    hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st,
-                       a, plan, t, P, npb);
-  else
-    hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, false, FFT_TH, PTS>), dim3((unsigned)nwg), dim3(FFT_TH), lds, st,
-                       a, plan, t, P, npb);
+  const bool half = is_half(a.r_ifft) || is_half(a.r_unpad);
+  const dim3 g((unsigned)nwg), blk(TH);
+  if (plan_has7(plan)) {
+    if (half) hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+    else hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+  } else {
+    if (half) hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, false, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+    else hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, false, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+  }
   return hipGetLastError();
 }
 
 template <class TI, class TC>
 static hipError_t irfft_go(const IrfftArgs& a, const FftPlan& plan, const void* tw, hipStream_t st) {
-  if (plan.N <= FFT_SMALL_PTS) return irfft_go_shape<TI, TC, FFT_SMALL_PTS>(a, plan, tw, st);
-  return irfft_go_shape<TI, TC, FFT_POINTS>(a, plan, tw, st);
+  if constexpr (sizeof(TC) == 4) {
+    // the inverse transform gains from the wider shape (longer output rows
+    // per workgroup) once there are enough workgroups to fill the chip
+    const int64_t wide_wgs = (a.S + 2 * pairs_per_wg(plan.N, a.S, FTM_FFT_F32_PTS, FTM_FFT_F32_TH) - 1) /
+                             (2 * pairs_per_wg(plan.N, a.S, FTM_FFT_F32_PTS, FTM_FFT_F32_TH)) * a.nrhs;
+    if (plan.N <= FTM_FFT_F32_SMALL_PTS && wide_wgs < 1024)
+      return irfft_go_shape<TI, TC, FTM_FFT_F32_SMALL_PTS, FTM_FFT_F32_TH>(a, plan, tw, st);
+    return irfft_go_shape<TI, TC, FTM_FFT_F32_PTS, FTM_FFT_F32_TH>(a, plan, tw, st);
+  } else {
+    if (plan.N <= FTM_FFT_SMALL_PTS) return irfft_go_shape<TI, TC, FTM_FFT_SMALL_PTS, FTM_FFT_TH>(a, plan, tw, st);
+    return irfft_go_shape<TI, TC, FFT_POINTS, FTM_FFT_TH>(a, plan, tw, st);
+  }
 }
 
 hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan, const void* tw,
