@@ -73,16 +73,23 @@ ftm_status check_precision(const ftm_precision& p) {
 
 const ftm_precision kAllF64 = {DT_F64, DT_F64, DT_F64, DT_F64, DT_F64, DT_F64};
 
-// Radices of a length-N plan: powers of two in radix-8 passes (a radix-4 pair
-// or one radix-4/radix-2 pass takes the remainder), then 5, 3 and 7.
-bool make_plan(int N, FftPlan* plan) {
+// Radices of a length-N plan: the factor 2^e2 in as few passes as radices up to
+// 2^maxbits allow, its bits spread evenly over them (larger radices first),
+// then 5, 3 and 7.  float32 transforms take radix 16 (maxbits 4); float64
+// ones stop at radix 8, whose registers leave room for more waves per SIMD.
+#ifndef FTM_FFT_RADIX16
+#define FTM_FFT_RADIX16 1
+#endif
+bool make_plan(int N, int maxbits, FftPlan* plan) {
   int n = N, e2 = 0;
   std::vector<int> rad;
   while (n % 2 == 0) { n /= 2; ++e2; }
-  if (e2 % 3 == 1 && e2 >= 4) { rad.push_back(4); rad.push_back(4); e2 -= 4; }
-  while (e2 >= 3) { rad.push_back(8); e2 -= 3; }
-  if (e2 == 2) rad.push_back(4);
-  if (e2 == 1) rad.push_back(2);
+  const int np = (e2 + maxbits - 1) / maxbits;
+  for (int i = 0; i < np; ++i) {
+    const int bits = (e2 + (np - i) - 1) / (np - i);  // ceil of the remaining bits over the remaining passes
+    rad.push_back(1 << bits);
+    e2 -= bits;
+  }
   for (int r : {5, 3, 7})
     while (n % r == 0) { n /= r; rad.push_back(r); }
   if (n != 1 || (int)rad.size() > MAX_STAGES) return false;
@@ -91,7 +98,7 @@ bool make_plan(int N, FftPlan* plan) {
   int Ns = 1;
   for (int i = 0; i < plan->nst; ++i) {
     plan->rad[i] = rad[i];
-    plan->div_nb[i] = make_fastdiv((uint32_t)(N / rad[i]));
+    plan->toff[i] = Ns == 1 ? 0 : plan->toff[i - 1] + Ns;  // pass i-1 took Ns = Ns_{i-1} * rad[i-1] entries
     plan->div_ns[i] = make_fastdiv((uint32_t)Ns);
     Ns *= rad[i];
   }
@@ -133,20 +140,31 @@ void release(ftm_operator op) {
   dev_free(&op->dhat);
 }
 
-// Twiddle tables exp(-2 pi i e / L), evaluated in long double and rounded once.
-ftm_status upload_twiddles(ftm_operator op, hipStream_t st) {
-  const int64_t L = op->L;
-  std::vector<double> t64(2 * L);
-  std::vector<float> t32(2 * L);
+// Per-pass twiddle tables of a plan (see FftPlan): exp(-2 pi i q jm / (Ns R))
+// evaluated in long double and rounded once to T.
+template <class T>
+std::vector<T> twiddle_table(const FftPlan& pl) {
+  std::vector<T> t(2 * (size_t)pl.twiddle_entries());
   const long double two_pi = 6.283185307179586476925286766559005768L;
-  for (int64_t e = 0; e < L; ++e) {
-    const long double ang = two_pi * (long double)e / (long double)L;
-    const long double c = cosl(ang), s = -sinl(ang);
-    t64[2 * e] = (double)c;
-    t64[2 * e + 1] = (double)s;
-    t32[2 * e] = (float)c;
-    t32[2 * e + 1] = (float)s;
+  int Ns = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.rad[s];
+    for (int jm = 0; jm < Ns; ++jm)
+      for (int q = 0; q < R; ++q) {
+        const long double ang = two_pi * (long double)(q * jm) / (long double)(Ns * R);
+        const size_t e = (size_t)pl.toff[s] + (size_t)jm * R + q;
+        t[2 * e] = (T)cosl(ang);
+        t[2 * e + 1] = (T)-sinl(ang);
+      }
+    Ns *= R;
   }
+  return t;
+}
+
+// float64 transforms run op->plan, float32 ones op->plan32.
+ftm_status upload_twiddles(ftm_operator op, hipStream_t st) {
+  const std::vector<double> t64 = twiddle_table<double>(op->plan);
+  const std::vector<float> t32 = twiddle_table<float>(op->plan32);
   ftm_status s;
   if ((s = dev_alloc(&op->tw64, t64.size() * sizeof(double))) != FTM_OK) return s;
   if ((s = dev_alloc(&op->tw32, t32.size() * sizeof(float))) != FTM_OK) return s;
@@ -241,7 +259,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io,
   const void* tw_in = p.fft == DT_F64 ? op->tw64.p : op->tw32.p;
   Profiler prof(op, st, adjoint ? 1 : 0);
   prof.mark(0);
-  FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, op->plan, tw_in, st));
+  FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, p.fft == DT_F64 ? op->plan : op->plan32, tw_in, st));
 
   GemvArgs ga{};
   ga.F = F;
@@ -290,7 +308,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io,
   ia.r_unpad = p.unpad;
   const void* tw_out = p.ifft == DT_F64 ? op->tw64.p : op->tw32.p;
   prof.mark(2);
-  FTM_HIP(launch_irfft(y_hat64, p.ifft == DT_F64, ia, op->plan, tw_out, st));
+  FTM_HIP(launch_irfft(y_hat64, p.ifft == DT_F64, ia, p.ifft == DT_F64 ? op->plan : op->plan32, tw_out, st));
   prof.mark(3);
   return FTM_OK;
 }
@@ -330,8 +348,8 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     ftm_status s;
     if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
 
-    FftPlan plan{};
-    if (!make_plan((int)(2 * Nt), &plan))
+    FftPlan plan{}, plan32{};
+    if (!make_plan((int)(2 * Nt), 3, &plan) || !make_plan((int)(2 * Nt), FTM_FFT_RADIX16 ? 4 : 3, &plan32))
       return fail(FTM_ERR_UNSUPPORTED, "2*Nt must factor into 2, 3, 5 and 7");
 
     ftm_operator op = new ftm_operator_s();
@@ -344,6 +362,7 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     op->ldd = (int)((Nd + 7) / 8 * 8);
     op->max_rhs = max_rhs;
     op->plan = plan;
+    op->plan32 = plan32;
     op->fwd = pf;
     op->adj = pa;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -2,14 +2,14 @@
 // unpadding (phases 4+5) fused in, for gfx950.
 //
 // Each workgroup holds P complex series of length N = L in LDS and runs a
-// mixed-radix (2, 3, 4, 5, 7, 8) self-sorting Stockham FFT on them: every
+// mixed-radix (2, 3, 4, 5, 7, 8, 16) self-sorting Stockham FFT on them: every
 // pass reads R points at stride N/R, applies the twiddles, does an R-point
 // DFT in registers and writes the results back in sorted order (the
 // formulation of Govindaraju et al., SC'08).  Two real series share one
 // complex transform (real part / imaginary part) and are separated with the
 // conjugate symmetry of real spectra afterwards, so P complex series carry 2P
-// of the caller's real series.  Twiddles come from a table computed on the
-// host in long double.
+// of the caller's real series.  Twiddles come from per-pass tables computed on
+// the host in long double.
 #include "ftm_device.h"
 #include "ftm_kernels.h"
 
@@ -138,6 +138,39 @@ __device__ __forceinline__ void dft8(cplx<T>* a) {
   }
 }
 
+// 16 = 4 x 4: length-4 DFTs over n1 (n = 4 n1 + n2), the twiddles
+// exp(-2 pi i n2 k1 / 16), then length-4 DFTs over n2 giving bin k1 + 4 k2.
+template <class T>
+__device__ __forceinline__ void dft16(cplx<T>* a) {
+  const T c1 = (T)0.9238795325112867561281832;  // cos(pi/8)
+  const T s1 = (T)0.3826834323650897717284600;  // sin(pi/8)
+  const T h = (T)0.7071067811865475244008444;   // sqrt(1/2)
+  cplx<T> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cplx<T> c[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+    dft4(c);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) y[k1][n2] = c[k1];
+  }
+  // y[k1][n2] *= exp(-2 pi i n2 k1 / 16) for the exponents 1, 2, 3, 4, 6, 9
+  y[1][1] = {c1 * y[1][1].x + s1 * y[1][1].y, c1 * y[1][1].y - s1 * y[1][1].x};
+  y[2][1] = {h * (y[2][1].x + y[2][1].y), h * (y[2][1].y - y[2][1].x)};
+  y[3][1] = {s1 * y[3][1].x + c1 * y[3][1].y, s1 * y[3][1].y - c1 * y[3][1].x};
+  y[1][2] = {h * (y[1][2].x + y[1][2].y), h * (y[1][2].y - y[1][2].x)};
+  y[2][2] = mul_mi(y[2][2]);
+  y[3][2] = {h * (y[3][2].y - y[3][2].x), -h * (y[3][2].x + y[3][2].y)};
+  y[1][3] = {s1 * y[1][3].x + c1 * y[1][3].y, s1 * y[1][3].y - c1 * y[1][3].x};
+  y[2][3] = {h * (y[2][3].y - y[2][3].x), -h * (y[2][3].x + y[2][3].y)};
+  y[3][3] = {-c1 * y[3][3].x - s1 * y[3][3].y, s1 * y[3][3].x - c1 * y[3][3].y};
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    dft4(y[k1]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = y[k1][k2];
+  }
+}
+
 template <int R, class T>
 __device__ __forceinline__ void dft(cplx<T>* a) {
   if constexpr (R == 2) dft2(a);
@@ -145,39 +178,63 @@ __device__ __forceinline__ void dft(cplx<T>* a) {
   else if constexpr (R == 4) dft4(a);
   else if constexpr (R == 5) dft5(a);
   else if constexpr (R == 7) dft7(a);
+  else if constexpr (R == 16) dft16(a);
   else dft8(a);
 }
 
+#ifndef FTM_FFT_NOHOIST
+#define FTM_FFT_NOHOIST 1
+#endif
+
+// Twiddle of a stage table entry: base[idx] with a 32-bit byte offset from a
+// uniform base (no 64-bit address arithmetic per load).
+template <class T>
+__device__ __forceinline__ cplx<T> tw_at(const cplx<T>* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(base) +
+                                           (size_t)(idx * (uint32_t)sizeof(cplx<T>)));
+}
+
 // One Stockham pass of radix R over P series of length N held in LDS.
-// Ns is the product of the radices of the earlier passes.  All reads of the
-// pass complete (barrier) before any write, so the pass works in place.
+// Ns is the product of the radices of the earlier passes.  2^lt threads work
+// on each series: thread tid takes series tid >> lt and the butterflies
+// j = (tid mod 2^lt) + i 2^lt < N/R.  The stage's twiddles
+// exp(-2 pi i q jm / (Ns R)) sit at tws[jm R + q], jm = j mod Ns.  All reads
+// of the pass complete (barrier) before any write, so the pass works in place.
 template <int R, int TH, int PTS, class T>
-__device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns, FastDiv dnb, FastDiv dns,
-                                         const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int lt, int Ns, FastDiv dns,
+                                         const cplx<T>* __restrict__ tws) {
   constexpr int MAXB = (PTS / TH + R - 1) / R;  // butterflies per thread
   const int nb = N / R;
-  const int total = P * nb;
-  const int tstride = N / (Ns * R);
+  const int tps = 1 << lt;
+  int tid = threadIdx.x;
+#if FTM_FFT_NOHOIST
+  // keep the per-pass LDS addresses from being hoisted out of the pass loop
+  // for every radix at once (that would cost occupancy for little gain)
+  asm volatile("" : "+v"(tid));
+#endif
+  const int base = (tid >> lt) * N, jj = tid & (tps - 1);
   cplx<T> v[MAXB][R];
+  int jms[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = threadIdx.x + i * TH;
-    if (b < total) {
-      const int p = (int)fast_div(b, dnb), j = b - p * nb, jm = j - (int)fast_div(j, dns) * Ns;
-      const int src = p * N + j;
+    const int j = jj + i * tps;
+    if (j < nb) {
+      const int jm = j - (int)fast_div(j, dns) * Ns;
+      jms[i] = jm;
+      const int src = base + j;
       v[i][0] = lds[lds_ix(src)];
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(src + q * nb)], tw[q * jm * tstride]);
+      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(src + q * nb)], tw_at(tws, (uint32_t)(jm * R + q)));
     }
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = threadIdx.x + i * TH;
-    if (b < total) {
+    const int j = jj + i * tps;
+    if (j < nb) {
       dft<R>(v[i]);
-      const int p = (int)fast_div(b, dnb), j = b - p * nb, jm = j - (int)fast_div(j, dns) * Ns;
-      const int dst = p * N + (j - jm) * R + jm;
+      const int jm = jms[i];
+      const int dst = base + (j - jm) * R + jm;
 #pragma unroll
       for (int q = 0; q < R; ++q) lds[lds_ix(dst + q * Ns)] = v[i][q];
     }
@@ -185,23 +242,28 @@ __device__ __forceinline__ void fft_pass(cplx<T>* lds, int N, int P, int Ns, Fas
   __syncthreads();
 }
 
-// Forward (unnormalised, exp(-2 pi i kt/N)) FFT of P series in LDS.  Plans
-// with a radix-7 pass use the R7 instantiation; the others do not carry its
-// register cost.
-template <class T, bool R7, int TH, int PTS>
+// Forward (unnormalised, exp(-2 pi i kt/N)) FFT of P series in LDS.  RX says
+// which of the costly radices the plan has (bit 0: 7, bit 1: 16); kernels for
+// plans without them do not carry their register cost.
+template <class T, int RX, int TH, int PTS>
 __device__ void fft_lds(cplx<T>* lds, const FftPlan& plan, int P, const cplx<T>* __restrict__ tw) {
+  const int lt = (31 - __clz(TH)) - (31 - __clz(P));  // log2(TH / P)
   int Ns = 1;
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.rad[s];
+    const cplx<T>* tws = tw + plan.toff[s];
     switch (R) {
-      case 2: fft_pass<2, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
-      case 3: fft_pass<3, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
-      case 4: fft_pass<4, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
-      case 5: fft_pass<5, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
+      case 2: fft_pass<2, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws); break;
+      case 3: fft_pass<3, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws); break;
+      case 4: fft_pass<4, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws); break;
+      case 5: fft_pass<5, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws); break;
       case 7:
-        if constexpr (R7) fft_pass<7, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw);
+        if constexpr ((RX & 1) != 0) fft_pass<7, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws);
         break;
-      default: fft_pass<8, TH, PTS>(lds, plan.N, P, Ns, plan.div_nb[s], plan.div_ns[s], tw); break;
+      case 16:
+        if constexpr ((RX & 2) != 0) fft_pass<16, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws);
+        break;
+      default: fft_pass<8, TH, PTS>(lds, plan.N, lt, Ns, plan.div_ns[s], tws); break;
     }
     Ns *= R;
   }
@@ -217,7 +279,7 @@ constexpr int FFT_LOAD_BATCH = 4;
 // the stores, so its addresses advance by a fixed stride: thread tid owns
 // column tid mod 2P and rows (or bins) tid / 2P, tid / 2P + TH / 2P, ...
 
-template <class TC, class TO, bool R7, bool HALF, int TH, int PTS>
+template <class TC, class TO, int RX, bool HALF, int TH, int PTS>
 __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
                                                                const cplx<TC>* __restrict__ tw,
                                                                int P, int64_t npb) {
@@ -256,7 +318,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
   }
   __syncthreads();
 
-  fft_lds<TC, R7, TH, PTS>(lds, plan, P, tw);
+  fft_lds<TC, RX, TH, PTS>(lds, plan, P, tw);
 
   // separate the two real spectra: X = (Z_k + conj Z_{N-k}) / 2,
   // Y = (Z_k - conj Z_{N-k}) / 2i; keep bins 0 .. N/2
@@ -293,7 +355,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
 
 // ---- phases 4+5: inverse real FFT + scale + unpad ---------------------------
 
-template <class TI, class TC, bool R7, bool HALF, int TH, int PTS>
+template <class TI, class TC, int RX, bool HALF, int TH, int PTS>
 __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan plan,
                                                                   const cplx<TC>* __restrict__ tw,
                                                                   int P, int64_t npb) {
@@ -352,7 +414,7 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
   }
   __syncthreads();
 
-  fft_lds<TC, R7, TH, PTS>(lds, plan, P, tw);
+  fft_lds<TC, RX, TH, PTS>(lds, plan, P, tw);
 
   const int j = tid & (two_p - 1), t0 = tid >> lg, tstep = TH >> lg;
   const int64_t s = s0 + j;
@@ -385,10 +447,14 @@ static int pairs_per_wg(int N, int64_t S, int pts, int threads) {
 
 static bool is_half(int dt) { return dt == DT_F16 || dt == DT_BF16; }
 
-static bool plan_has7(const FftPlan& plan) {
-  for (int i = 0; i < plan.nst; ++i)
-    if (plan.rad[i] == 7) return true;
-  return false;
+// radix set of a plan for the kernel instantiation: bit 0 radix 7, bit 1 radix 16
+static int plan_rx(const FftPlan& plan) {
+  int rx = 0;
+  for (int i = 0; i < plan.nst; ++i) {
+    if (plan.rad[i] == 7) rx |= 1;
+    if (plan.rad[i] == 16) rx |= 2;
+  }
+  return rx;
 }
 
 // Workgroup shapes.  float64: 512 threads over at most 2048 points (one
@@ -422,12 +488,12 @@ static hipError_t rfft_go_shape(const RfftArgs& a, const FftPlan& plan, const vo
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
   const bool half = is_half(a.r_pad) || is_half(a.r_fft) || is_half(a.r_next);
   const dim3 g((unsigned)nwg), blk(TH);
-  if (plan_has7(plan)) {
-    if (half) hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
-    else hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, true, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
-  } else {
-    if (half) hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, false, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
-    else hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, false, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+  switch (plan_rx(plan) * 2 + (half ? 1 : 0)) {
+#define FTM_RFFT_CASE(RX, H) \
+  case RX * 2 + H: hipLaunchKernelGGL((rfft_pad_kernel<TC, TO, RX, H, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb); break;
+    FTM_RFFT_CASE(0, 0) FTM_RFFT_CASE(0, 1) FTM_RFFT_CASE(1, 0) FTM_RFFT_CASE(1, 1)
+    FTM_RFFT_CASE(2, 0) FTM_RFFT_CASE(2, 1) FTM_RFFT_CASE(3, 0) FTM_RFFT_CASE(3, 1)
+#undef FTM_RFFT_CASE
   }
   return hipGetLastError();
 }
@@ -460,12 +526,12 @@ static hipError_t irfft_go_shape(const IrfftArgs& a, const FftPlan& plan, const 
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
   const bool half = is_half(a.r_ifft) || is_half(a.r_unpad);
   const dim3 g((unsigned)nwg), blk(TH);
-  if (plan_has7(plan)) {
-    if (half) hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
-    else hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, true, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
-  } else {
-    if (half) hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, false, true, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
-    else hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, false, false, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb);
+  switch (plan_rx(plan) * 2 + (half ? 1 : 0)) {
+#define FTM_IRFFT_CASE(RX, H) \
+  case RX * 2 + H: hipLaunchKernelGGL((irfft_unpad_kernel<TI, TC, RX, H, TH, PTS>), g, blk, lds, st, a, plan, t, P, npb); break;
+    FTM_IRFFT_CASE(0, 0) FTM_IRFFT_CASE(0, 1) FTM_IRFFT_CASE(1, 0) FTM_IRFFT_CASE(1, 1)
+    FTM_IRFFT_CASE(2, 0) FTM_IRFFT_CASE(2, 1) FTM_IRFFT_CASE(3, 0) FTM_IRFFT_CASE(3, 1)
+#undef FTM_IRFFT_CASE
   }
   return hipGetLastError();
 }

@@ -42,12 +42,17 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, FastDiv f) {
 }
 
 // Mixed-radix plan of a length-N complex FFT: N = rad[0] * rad[1] * ...
-// div_nb[s] divides by N / rad[s], div_ns[s] by rad[0] * .. * rad[s-1].
+// div_ns[s] divides by Ns = rad[0] * .. * rad[s-1].  Pass s reads its
+// twiddles exp(-2 pi i q jm / (Ns rad[s])) (jm < Ns, q < rad[s]) from the
+// twiddle table at toff[s] + jm * rad[s] + q; twiddle_entries() is the table
+// length.
 struct FftPlan {
   int N;
   int nst;
   int rad[MAX_STAGES];
-  FastDiv div_nb[MAX_STAGES], div_ns[MAX_STAGES];
+  int toff[MAX_STAGES];
+  FastDiv div_ns[MAX_STAGES];
+  int twiddle_entries() const { return nst ? toff[nst - 1] + N : 0; }
 };
 
 // Phases 1+2 (or the setup transform of F): real series x[b][t][s] (t < Nt,

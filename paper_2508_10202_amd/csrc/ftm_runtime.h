@@ -43,8 +43,8 @@ struct ftm_operator_s {
   int ldm = 0, ldd = 0;  // padded column counts of spectra and workspaces
   int device = 0;
   int64_t max_rhs = 1;
-  ftm::FftPlan plan{};
-  ftm_rt::DevBuf tw64, tw32;  // exp(-2 pi i e / L), e = 0 .. L-1
+  ftm::FftPlan plan{}, plan32{};  // length-L plans of the float64 and float32 transforms
+  ftm_rt::DevBuf tw64, tw32;     // their per-pass twiddle tables
   ftm_rt::DevBuf spec[4];     // Fhat[K][Nd][ldm] per storage format
   ftm_rt::DevBuf mhat, dhat;  // the operator's own workspace, sized for max_rhs
   ftm_precision fwd{}, adj{};

@@ -74,6 +74,28 @@ def test_ragged_shapes_fp64(gpu, s):
     assert _rel(out["m"], oracle.adjoint(F, d)) <= FP64_TOL
 
 
+# float32 transforms run their own plans (radix-16 passes for the factor 2^e):
+# the ragged shapes again, plus lengths whose plans are 16, 16*5 and 16*16*8
+RAGGED_F32 = RAGGED + [
+    Shape(8, 3, 11, decay=None),      # L = 16
+    Shape(40, 5, 70, decay=20.0),     # L = 80 = 16*5
+    Shape(1024, 3, 17, decay=300.0),  # L = 2048 = 16*16*8
+]
+
+
+@pytest.mark.parametrize("prec", ["dsdsd", "sssss"])
+@pytest.mark.parametrize("s", RAGGED_F32, ids=lambda s: f"Nt{s.Nt}_Nd{s.Nd}_Nm{s.Nm}")
+def test_ragged_shapes_fp32_transforms(gpu, s, prec):
+    _say("case ragged float32 transforms", s, prec)
+    F, m, d = make_F(s, 14), make_m(s, 15)[0], make_d(s, 16)[0]
+    out = _run(F, m, d, fwd=prec, adj=prec)
+    e_f, e_a = _rel(out["d"], oracle.forward(F, m)), _rel(out["m"], oracle.adjoint(F, d))
+    _, hi_f = mp_bounds(prec, s.L, s.Nm)
+    _, hi_a = mp_bounds(prec, s.L, s.Nd)
+    _say(f"  {prec}: fwd {e_f:.3e} <= {hi_f:.1e}, adj {e_a:.3e} <= {hi_a:.1e}")
+    assert e_f <= hi_f and e_a <= hi_a
+
+
 def test_identity_and_delay_blocks_exact(gpu):
     """F_0 = I gives d = m, F_2 = I a two-block delay (up to float64 rounding of the FFTs)."""
     Nt, n = 30, 8
