@@ -32,7 +32,9 @@ sys.path.insert(0, ROOT)
 METRIC = "matvecs/s + HBM GB/s at N_t=1000,N_d=100,N_m=5000; FP64 vs mixed @rel err"
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemv_fwd_f64_paper_traffic.json")
-GEMV_SRC = os.path.join(ROOT, "paper_2508_10202_amd", "csrc", "ftm_gemv.hip")
+# sources the product kernels are compiled from (the counters go stale when any changes)
+GEMV_SRCS = [os.path.join(ROOT, "paper_2508_10202_amd", "csrc", f)
+             for f in ("ftm_gemv.hip", "ftm_device.h", "ftm_kernels.h")]
 
 # configurations timed by default: the paper's 32 {d,s} assignments plus
 # half-precision storage variants (all in execution order pad,fft,gemv,ifft,unpad)
@@ -74,6 +76,14 @@ def pareto(rows):
     return front
 
 
+def gemv_source_sha256():
+    h = hashlib.sha256()
+    for f in GEMV_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic_record():
     """HBM traffic of the dominant kernel from committed PMC counter runs, if
     they were taken on the current kernel source; else None."""
@@ -81,7 +91,7 @@ def traffic_record():
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
-    sha = hashlib.sha256(open(GEMV_SRC, "rb").read()).hexdigest()
+    sha = gemv_source_sha256()
     if rec.get("kernel_source_sha256") != sha:
         return None
     return rec.get("bytes_per_launch")
