@@ -126,7 +126,9 @@ ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs);
  * configuration (one vector, reps timed runs each, on scratch inputs) and
  * keep the fastest.  Synchronises the stream.  The choice is kept per
  * direction and storage format; ftm_get_tuning / ftm_set_tuning read and set
- * it (for a persistent tuning cache kept by the caller). */
+ * it (for a persistent tuning cache kept by the caller).  Variants are
+ * numbered 0 .. 3 per direction (0 is the default); other values are
+ * FTM_ERR_INVALID. */
 ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream);
 ftm_status ftm_get_tuning(ftm_operator op, int32_t* fwd_variant, int32_t* adj_variant, double* fwd_ms,
                           double* adj_ms);

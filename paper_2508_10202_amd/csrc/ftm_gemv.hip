@@ -236,9 +236,10 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_adj_kernel(GemvArgs a, int 
 // ---- host launchers -----------------------------------------------------------
 
 // Tile-shape variants (chosen per operator by the autotuner):
-//   forward  0: 4 rows per workgroup (default), 1: 2 rows, 2: 8 rows
+//   forward  0: 4 rows per workgroup (default), 1: 2 rows, 2: 8 rows, 3: 16 rows
 //   adjoint  0: 4 waves split the rows (default), 1: 2 waves split the rows
-//            (2 column groups), 2: 4 waves split the rows, 2 chunks per lane
+//            (2 column groups), 2: 4 waves split the rows, 2 chunks per lane,
+//            3: 4 waves split the rows, 4 chunks per lane
 template <class S, class TA, class TI, class TO, int R>
 static hipError_t fwd_go_r(const GemvArgs& a, hipStream_t st) {
   const int nrb = (a.Nd + R - 1) / R;
@@ -253,6 +254,7 @@ static hipError_t fwd_go(const GemvArgs& a, hipStream_t st) {
   switch (a.variant) {
     case 1: return fwd_go_r<S, TA, TI, TO, 2>(a, st);
     case 2: return fwd_go_r<S, TA, TI, TO, 8>(a, st);
+    case 3: return fwd_go_r<S, TA, TI, TO, 16>(a, st);
     default: return fwd_go_r<S, TA, TI, TO, FWD_ROWS>(a, st);
   }
 }
@@ -274,6 +276,7 @@ static hipError_t adj_go(const GemvArgs& a, hipStream_t st) {
   switch (a.variant) {
     case 1: return adj_go_l<S, TA, TI, TO, 2, 1>(a, st);
     case 2: return adj_go_l<S, TA, TI, TO, 4, 2>(a, st);
+    case 3: return adj_go_l<S, TA, TI, TO, 4, 4>(a, st);
     default: return adj_go_l<S, TA, TI, TO, FTM_ADJ_RW, FTM_ADJ_CPT>(a, st);
   }
 }

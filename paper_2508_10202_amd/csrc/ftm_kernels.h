@@ -103,7 +103,7 @@ struct GemvArgs {
 };
 
 // Number of tile-shape variants of the matrix-vector kernels.
-constexpr int GEMV_VARIANTS = 3;
+constexpr int GEMV_VARIANTS = 4;
 
 hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
                        const void* tw, hipStream_t st);

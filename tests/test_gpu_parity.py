@@ -400,16 +400,26 @@ def test_autotune_keeps_results_and_caches(gpu, tmp_path):
     from paper_2508_10202_amd import Operator
     s = Shape(100, 37, 1000)
     F, m, d = make_F(s, 111), make_m(s, 112)[0], make_d(s, 113)[0]
-    op = Operator(torch.from_numpy(F).cuda())
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s",))
     cache = str(tmp_path / "tune.json")
     rec = op.autotune(reps=3, cache=cache)
-    assert not rec["cached"] and 0 <= rec["fwd_variant"] < 3 and 0 <= rec["adj_variant"] < 3
+    assert not rec["cached"] and 0 <= rec["fwd_variant"] < 4 and 0 <= rec["adj_variant"] < 4
     assert rec["fwd_ms"] > 0 and rec["adj_ms"] > 0
     assert op.autotune(cache=cache)["cached"]
     mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
     ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
-    for v in range(3):                          # every variant computes the same product
-        op.set_tuning(v, v)
-        assert _rel(op.matvec(mt).cpu().numpy(), ref_d) <= FP64_TOL
-        assert _rel(op.rmatvec(dt).cpu().numpy(), ref_m) <= FP64_TOL
+    for prec, tol in (("ddddd", FP64_TOL), ("sssss", mp_bounds("sssss", s.L, s.Nm)[1])):
+        op.set_precision(fwd=prec, adj=prec)
+        outs = []
+        for v in range(4):                      # every variant computes the same product
+            op.set_tuning(v, v)
+            yd, ym = op.matvec(mt).cpu().numpy(), op.rmatvec(dt).cpu().numpy()
+            assert _rel(yd, ref_d) <= tol and _rel(ym, ref_m) <= tol, (prec, v)
+            outs.append((yd, ym))
+        if prec == "ddddd":                     # same summation order within each output
+            for yd, ym in outs[1:]:
+                assert _rel(yd, outs[0][0]) <= 1e-14 and _rel(ym, outs[0][1]) <= 1e-14
+    from paper_2508_10202_amd import FtmError
+    with pytest.raises(FtmError):
+        op.set_tuning(4, 0)
     op.close()
