@@ -76,7 +76,18 @@ __device__ __forceinline__ void store_c(float* y, float re, float im, int r_gemv
 // ---------------------------------------------------------------------------
 // forward, FP32 storage: MFMA 16x16x4 f32
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
+// NW waves per workgroup, 16 spectrum rows each.  Fewer waves per workgroup
+// give more, smaller workgroups: with K = Nt + 1 frequencies the workgroup
+// count is rarely a multiple of the CU count, and the CUs that take one
+// workgroup more set the kernel's time.
+#ifndef FTM_GEMM_FWD_NW
+#define FTM_GEMM_FWD_NW 4
+#endif
+constexpr int GEMM_FWD_NW = FTM_GEMM_FWD_NW;
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
+  constexpr int TH = 64 * NW;
   __shared__ float xs[GEMM_BM][KC + LDS_PAD];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * nrb;
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_f32_kernel(GemvArgs a, 
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, r0 = rb * FWD_BN + w * 16;
+  const int b0 = bb * GEMM_BM, r0 = (rb * NW + w) * 16;
   const int kr = 2 * a.ld;  // reals per row
 
   const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
@@ -97,21 +108,31 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_f32_kernel(GemvArgs a, 
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // cooperative X' staging: 64 rows x 64 reals = 1024 float4, 4 per thread
-  const int st_row = threadIdx.x >> 2, st_col = (threadIdx.x & 3) * 4;
-  const int xb = min(b0 + st_row, a.nrhs - 1);
-  const float* __restrict__ xsrc = X + xb * xrow;
+  // cooperative X' staging: 64 rows x 64 reals = 1024 float4; float4 e goes
+  // to row e / 16, reals 4 (e mod 16) .. +3, so 16 threads read one row's 256 B
+  constexpr int NST = 1024 / TH;
+  const float* __restrict__ xsrc[NST];
+  int st_row[NST], st_col[NST];
+#pragma unroll
+  for (int q = 0; q < NST; ++q) {
+    const int e = threadIdx.x + TH * q;
+    st_row[q] = e >> 4;
+    st_col[q] = (e & 15) * 4;
+    xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
+  }
 
   for (int kc = 0; kc < kr; kc += KC) {
     // stage X'[b0..b0+64)[kc..kc+64) (zero past the row end)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int col = kc + st_col + 16 * q;
+    for (int q = 0; q < NST; ++q) {
+      const int col = kc + st_col[q];
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (col < kr) v = *reinterpret_cast<const float4*>(xsrc + col);
-      *reinterpret_cast<float4*>(&xs[st_row][st_col + 16 * q]) = v;
+      if (col < kr) v = *reinterpret_cast<const float4*>(xsrc[q] + col);
+      *reinterpret_cast<float4*>(&xs[st_row[q]][st_col[q]]) = v;
     }
-    // this wave's spectrum rows, the same 64 reals, in MFMA order
+    // this wave's spectrum rows, the same 64 reals, in MFMA order (no
+    // prefetch of the next chunk: its registers would cost two waves per SIMD,
+    // which measured slower)
     uint4 fv[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -271,27 +292,44 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
-    // spectrum tile: 32 rows x 64 columns, two complex per 16-byte load
+  // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
+  // on chunk r0: the spectrum tile (32 rows x 64 columns, two complex per
+  // 16-byte load) and the data tile (64 right-hand sides x 32 sensors).
+  float4 fv[4];
+  cplx<float> xv[8];
+  auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int row = idx >> 5, col = (idx & 31) * 2;
       const int r = r0 + row, c = c0 + col;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < a.Nd && c < a.ld) v = __builtin_bit_cast(float4, load_stream(Fk + (int64_t)r * a.ld + c));
-      fs[row][col] = {v.x, v.y};
-      fs[row][col + 1] = {v.z, v.w};
+      fv[q] = (r < a.Nd && c < a.ld) ? __builtin_bit_cast(float4, load_stream(Fk + (int64_t)r * a.ld + c))
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // data tile: 64 right-hand sides x 32 sensors
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
-      xs[bl][rr] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+    }
+  };
+  load_chunk(0);
+  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx >> 5, col = (idx & 31) * 2;
+      fs[row][col] = {fv[q].x, fv[q].y};
+      fs[row][col + 1] = {fv[q].z, fv[q].w};
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      xs[idx >> 5][idx & 31] = xv[q];
     }
     __syncthreads();
+    if (r0 + RC < a.Nd) load_chunk(r0 + RC);
 #pragma unroll
     for (int s = 0; s < RC / 4; ++s) {
       const cplx<float> f = fs[4 * s + g][w * 16 + l16];
@@ -342,30 +380,47 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
-    // spectrum tile: 32 rows x 64 columns, four complex per 16-byte load
+  // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
+  // on chunk r0: the spectrum tile (32 rows x 64 columns, four complex per
+  // 16-byte load) and the data tile (64 right-hand sides x 32 sensors).
+  uint4 fv[2];
+  cplx<float> xv[8];
+  auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int row = idx >> 4, col = (idx & 15) * 4;
       const int r = r0 + row, c = c0 + col;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (r < a.Nd && c < a.ld) v = load_stream(Fk + (int64_t)r * a.ld + c);
-      fs[row][col] = v.x;
-      fs[row][col + 1] = v.y;
-      fs[row][col + 2] = v.z;
-      fs[row][col + 3] = v.w;
+      fv[q] = (r < a.Nd && c < a.ld) ? load_stream(Fk + (int64_t)r * a.ld + c) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
-      const cplx<float> x = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
-      xr16[bl][rr] = (uint16_t)to_bits16<H>(x.x);  // exact: x holds values of the 16-bit format
-      xi16[bl][rr] = (uint16_t)to_bits16<H>(x.y);
+      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+    }
+  };
+  load_chunk(0);
+  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx >> 4, col = (idx & 15) * 4;
+      fs[row][col] = fv[q].x;
+      fs[row][col + 1] = fv[q].y;
+      fs[row][col + 2] = fv[q].z;
+      fs[row][col + 3] = fv[q].w;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int bl = idx >> 5, rr = idx & 31;
+      xr16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].x);  // exact: x holds values of the 16-bit format
+      xi16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].y);
     }
     __syncthreads();
+    if (r0 + RC < a.Nd) load_chunk(r0 + RC);
     // B operands: fr and fi of sensors 8 g .. 8 g + 7 at this lane's column
     uint4 ufr, ufi;
     uint32_t* pr = reinterpret_cast<uint32_t*>(&ufr);
@@ -410,12 +465,20 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
 // ---- host launchers -----------------------------------------------------------
 
 hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st) {
-  const int nbb = (a.nrhs + GEMM_BM - 1) / GEMM_BM, nrb = (a.Nd + FWD_BN - 1) / FWD_BN;
+  const int nbb = (a.nrhs + GEMM_BM - 1) / GEMM_BM;
+  if (fdt == DT_F32) {
+    const int nrb = (a.Nd + 16 * GEMM_FWD_NW - 1) / (16 * GEMM_FWD_NW);
+    const int64_t nwg = (int64_t)a.K * nbb * nrb;
+    if (nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_fwd_f32_kernel<GEMM_FWD_NW>, dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0, st, a, nbb,
+                       nrb);
+    return hipGetLastError();
+  }
+  const int nrb = (a.Nd + FWD_BN - 1) / FWD_BN;
   const int64_t nwg = (int64_t)a.K * nbb * nrb;
   if (nwg <= 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
-    case DT_F32: hipLaunchKernelGGL(gemm_fwd_f32_kernel, grid, block, 0, st, a, nbb, nrb); break;
     case DT_F16: hipLaunchKernelGGL(gemm_fwd_h_kernel<s_f16>, grid, block, 0, st, a, nbb, nrb); break;
     case DT_BF16: hipLaunchKernelGGL(gemm_fwd_h_kernel<s_bf16>, grid, block, 0, st, a, nbb, nrb); break;
     default: return hipErrorInvalidValue;
