@@ -203,29 +203,45 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  const int st_row = threadIdx.x >> 2, st_col = (threadIdx.x & 3) * 4;
-  const int xb = min(b0 + st_row, a.nrhs - 1);
-  const float* __restrict__ xsrc = X + xb * xrow;
-
-  for (int kc = 0; kc < kr; kc += KC) {
+  // X' staging: float4 e (of 1024 per chunk) goes to row e / 16, reals
+  // 4 (e mod 16) .. +3, so 16 threads read one row's 256 B.  Chunk kc + KC is
+  // loaded into registers while the matrix cores work on chunk kc.
+  int st_row[4], st_col[4];
+  const float* __restrict__ xsrc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + GEMM_THREADS * q;
+    st_row[q] = e >> 4;
+    st_col[q] = (e & 15) * 4;
+    xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
+  }
+  float4 xv[4];
+  uint4 fn[2];
+  auto load_chunk = [&](int kc) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int col = kc + st_col + 16 * q;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (col < kr) v = *reinterpret_cast<const float4*>(xsrc + col);
-      uint16_t* d = &xs[st_row][st_col + 16 * q];
-      d[0] = (uint16_t)to_bits16<H>(v.x);
-      d[1] = (uint16_t)to_bits16<H>(v.y);
-      d[2] = (uint16_t)to_bits16<H>(v.z);
-      d[3] = (uint16_t)to_bits16<H>(v.w);
+      const int col = kc + st_col[q];
+      xv[q] = col < kr ? *reinterpret_cast<const float4*>(xsrc[q] + col) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    uint4 fv[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int col = kc + 32 * s + 8 * g;
-      fv[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+      fn[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
     }
+  };
+  load_chunk(0);
+  for (int kc = 0; kc < kr; kc += KC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint16_t* d = &xs[st_row[q]][st_col[q]];
+      d[0] = (uint16_t)to_bits16<H>(xv[q].x);
+      d[1] = (uint16_t)to_bits16<H>(xv[q].y);
+      d[2] = (uint16_t)to_bits16<H>(xv[q].z);
+      d[3] = (uint16_t)to_bits16<H>(xv[q].w);
+    }
+    uint4 fv[2] = {fn[0], fn[1]};
     __syncthreads();
+    if (kc + KC < kr) load_chunk(kc + KC);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       // each 32-bit word is (re | im << 16): Fr' flips the sign of im, Fi' swaps
