@@ -187,7 +187,14 @@ ftm_status ftm_destroy_operator(ftm_operator op);
  * Results are the same, within the precision configuration's tolerance, as
  * a lone ftm_matvec/ftm_rmatvec of the same input (bitwise when the product
  * takes the same path; see ftm_set_rhs_mode).
- * The operators' precision configuration is read when a batch launches. */
+ * The operators' precision configuration is read when a batch launches, and
+ * so is a batch's workspace size: K * nrhs * (ldm * e_m + ldd * e_d) bytes
+ * (plus alignment), where e_m and e_d are 16 for a transformed vector stored
+ * in float64 (both neighbouring phases float64) and 8 otherwise, ldm and ldd
+ * being Nm and Nd rounded up to 8.  A queued request that no longer fits the
+ * whole budget at its operator's configuration when it reaches the head of
+ * the queue fails (FTM_ERR_HIP from ftm_server_wait / poll, with the reason
+ * in ftm_last_error) instead of waiting forever. */
 typedef struct ftm_server_s* ftm_server;
 
 typedef struct ftm_server_stats {
@@ -210,7 +217,8 @@ ftm_status ftm_server_create(ftm_server* out, size_t workspace_budget, int32_t n
  * is waited for on the device before x is read: record it on the stream that
  * produced x.  The caller keeps x, y and the event alive, and x and y
  * untouched, until the ticket completes.  FTM_ERR_BUDGET: the request alone
- * needs more workspace than the whole budget (it would never run). */
+ * needs more workspace than the whole budget at the operator's current
+ * configuration (it would never run). */
 ftm_status ftm_server_submit(ftm_server s, ftm_operator op, int32_t adjoint, const double* x, double* y,
                              int64_t nrhs, void* ready_event, uint64_t* ticket);
 

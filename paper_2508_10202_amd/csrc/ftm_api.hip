@@ -35,12 +35,13 @@ ftm_status fail_hip(const char* what, hipError_t e) {
   return fail(FTM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs) {
+Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs, bool adjoint) {
+  int em, ed;
+  op->workspace_elems(adjoint, &em, &ed);
   Workspace w;
   char* p = reinterpret_cast<char*>(base);
   w.mhat = p;
-  const size_t m_bytes = ((size_t)op->K * nrhs * op->ldm * 16 + 255) / 256 * 256;
-  w.dhat = p + m_bytes;
+  w.dhat = p + ftm_operator_s::round256((size_t)op->K * nrhs * op->ldm * em);
   return w;
 }
 

@@ -67,9 +67,27 @@ struct ftm_operator_s {
     for (const auto& s : spec) b += s.n;
     return b;
   }
-  // workspace bytes a matvec of nrhs right-hand sides needs
+  // workspace bytes a matvec of nrhs right-hand sides needs in any precision
+  // configuration (float64 intermediates)
   size_t workspace_bytes(int64_t nrhs) const {
     return (size_t)K * nrhs * (ldm + ldd) * 16 + 512;
+  }
+  // bytes per complex entry of m-hat and d-hat in one direction at the
+  // current configuration: float64 (16) where both neighbouring phases are
+  // float64, else float32 (8)
+  void workspace_elems(bool adjoint, int* em, int* ed) const {
+    const ftm_precision& p = adjoint ? adj : fwd;
+    const int ex = (p.fft == 0 && p.gemv == 0) ? 16 : 8;   // transformed input
+    const int ey = (p.gemv == 0 && p.ifft == 0) ? 16 : 8;  // transformed output
+    *em = adjoint ? ey : ex;
+    *ed = adjoint ? ex : ey;
+  }
+  static size_t round256(size_t n) { return (n + 255) / 256 * 256; }
+  // workspace bytes of one matvec in one direction at the current configuration
+  size_t workspace_bytes(int64_t nrhs, bool adjoint) const {
+    int em, ed;
+    workspace_elems(adjoint, &em, &ed);
+    return round256((size_t)K * nrhs * ldm * em) + (size_t)K * nrhs * ldd * ed + 512;
   }
 };
 
@@ -100,8 +118,9 @@ class DeviceGuard {
   bool switched_ = false;
 };
 
-// Split a workspace block of op->workspace_bytes(nrhs) bytes.
-Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs);
+// Split a workspace block of op->workspace_bytes(nrhs, adjoint) bytes for a
+// matvec in that direction at the operator's current configuration.
+Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs, bool adjoint);
 
 // Enqueue one matvec (phases 1-5) on st.  No argument checks: callers
 // validate.

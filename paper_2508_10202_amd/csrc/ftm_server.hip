@@ -198,7 +198,7 @@ void ftm_server_s::launch(Slot& s, std::vector<Request>&& batch, size_t off, siz
     ftm_rt::MatvecIO io;
     io.xptr = reinterpret_cast<const double* const*>(s.d_ptrs);
     io.yptr = reinterpret_cast<double* const*>(s.d_ptrs) + max_batch_rhs;
-    const ftm_rt::Workspace ws = ftm_rt::carve_workspace(op, reinterpret_cast<char*>(arena_base) + off, nrhs);
+    const ftm_rt::Workspace ws = ftm_rt::carve_workspace(op, reinterpret_cast<char*>(arena_base) + off, nrhs, adj);
     st = ftm_rt::run_matvec(op, adj, io, nrhs, ws, s.stream);
     if (st == FTM_OK) e = hipLaunchHostFunc(s.stream, on_batch_done, &s.ctx);
   }
@@ -242,6 +242,17 @@ void ftm_server_s::run() {
         }
       if (!free_slot) break;
       const Request head = queue.front();
+      if (head.op->workspace_bytes(head.nrhs, head.adjoint) > budget) {
+        // the operator's precision changed after submit to one whose
+        // workspace exceeds the whole budget: this request can never run
+        error = "request needs more workspace than the whole budget at the operator's current precision";
+        state[head.ticket - 1] = ST_FAILED;
+        stats.failed += 1;
+        inflight_requests -= 1;
+        queue.erase(queue.begin());
+        cv_done.notify_all();
+        continue;
+      }
       std::vector<size_t> take{0};
       int64_t total = head.nrhs;
       for (size_t i = 1; i < queue.size() && total < max_batch_rhs; ++i) {
@@ -251,7 +262,7 @@ void ftm_server_s::run() {
           total += r.nrhs;
         }
       }
-      size_t off = 0, bytes = head.op->workspace_bytes(total);
+      size_t off = 0, bytes = head.op->workspace_bytes(total, head.adjoint);
       while (!arena.alloc(bytes, &off)) {
         // shrink the batch from the back until it fits; the head alone may
         // have to wait for running batches to release workspace
@@ -261,7 +272,7 @@ void ftm_server_s::run() {
         }
         total -= queue[take.back()].nrhs;
         take.pop_back();
-        bytes = head.op->workspace_bytes(total);
+        bytes = head.op->workspace_bytes(total, head.adjoint);
       }
       if (bytes == 0) {
         stats.budget_waits += 1;
@@ -346,8 +357,8 @@ ftm_status ftm_server_submit(ftm_server s, ftm_operator op, int32_t adjoint, con
   if (op->device != s->device) return fail(FTM_ERR_INVALID, "operator lives on another device");
   const ftm_precision& p = adjoint ? op->adj : op->fwd;
   if (!op->spec[p.gemv].p) return fail(FTM_ERR_STATE, "spectrum for the configured precision is missing");
-  if (op->workspace_bytes(nrhs) > s->budget)
-    return fail(FTM_ERR_BUDGET, "request needs " + std::to_string(op->workspace_bytes(nrhs)) +
+  if (op->workspace_bytes(nrhs, adjoint != 0) > s->budget)
+    return fail(FTM_ERR_BUDGET, "request needs " + std::to_string(op->workspace_bytes(nrhs, adjoint != 0)) +
                                     " workspace bytes, more than the whole budget");
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -126,6 +126,48 @@ def _ws(op, nrhs):
     return K * nrhs * (ldm + ldd) * 16 + 512 + 512
 
 
+def _ws32(op, nrhs):
+    """Workspace bytes of one batch whose transformed vectors are float32 (the
+    library's sizing, rounded to the arena's 256-byte grain)."""
+    K = op.Nt + 1
+    ldm, ldd = (op.Nm + 7) // 8 * 8, (op.Nd + 7) // 8 * 8
+    m = (K * nrhs * ldm * 8 + 255) // 256 * 256
+    return (m + K * nrhs * ldd * 8 + 512 + 255) // 256 * 256
+
+
+def test_float32_batches_take_float32_workspace(gpu, ops):
+    """With float32 intermediates a batch needs half the float64 workspace:
+    a budget that holds exactly one float32 batch of 8 vectors admits it (the
+    float64 sizing would reject it) and never exceeds the budget."""
+    import torch
+    from paper_2508_10202_amd import FtmError, Server
+    s, F, op = ops[1]
+    budget = _ws32(op, 8)
+    assert budget < _ws(op, 8)
+    x = normal((8, s.Nt, s.Nm), 4242)
+    xt = torch.from_numpy(x).cuda()
+    try:
+        op.set_precision(fwd="sssss", adj="sssss")
+        with Server(workspace_budget=budget, n_slots=2, max_batch_rhs=8) as srv:
+            tickets = [srv.submit(op, xt) for _ in range(3)]
+            for t, _ in tickets:
+                srv.wait(t, timeout=60)
+            st = srv.stats()
+            op.set_precision(fwd="ddddd", adj="ddddd")
+            with pytest.raises(FtmError) as ei:            # the float64 batch does not fit
+                srv.submit(op, xt)
+            assert ei.value.status == 4
+    finally:
+        op.set_precision(fwd="ddddd", adj="ddddd")
+    _say(f"  float32 workspace: budget {budget}, {st}")
+    assert st["completed"] == 3 and st["failed"] == 0
+    assert st["peak_workspace_bytes"] <= budget
+    ref = oracle.forward(F, x)
+    tol = 2e-5
+    for t, y in tickets:
+        assert oracle.relative_l2(y.cpu().numpy(), ref) <= tol
+
+
 def test_request_beyond_budget_is_rejected(gpu, ops):
     import torch
     from paper_2508_10202_amd import FtmError, Server
