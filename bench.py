@@ -167,7 +167,9 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
     """Poisson arrivals at `rate` req/s against 4 device-resident FP32
     operators; each request is forward or adjoint (50/50) with 1..32 vectors,
     operator uniform.  Workspace budget 4 GiB (it binds: a 32-vector request
-    on the largest operators needs 1.3-2.1 GB)."""
+    on the largest operators needs 1.3-2.1 GB).  A second, shorter run offers
+    the same mix at 3/4 of the throughput the first one reached
+    (`below_capacity`), where the latency is not dominated by queueing."""
     import numpy as np
     import torch
 
@@ -192,74 +194,81 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
             pools[i, adj] = [torch.randn((32, op.Nt, n), dtype=torch.float64, device=dev, generator=g)
                              for _ in range(2)]
     torch.cuda.synchronize()
-    rng = np.random.default_rng(seed_for(5, 4))
-    total = warmup + seconds
-    n_req = int(rate * total * 1.2) + 16
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
-    arrivals = arrivals[arrivals < total]
-    kinds = rng.integers(0, len(ops), len(arrivals))
-    dirs = rng.integers(0, 2, len(arrivals))
-    nrhs = rng.integers(1, 33, len(arrivals))
     budget = 4 << 30
-    srv = Server(workspace_budget=budget, n_slots=4, max_batch_rhs=64)
     # output buffers: a ring of 8 per (operator, direction), 32 vectors each; a
     # buffer is reused once the request that wrote it has completed (if it has
     # not, the client waits: that delay counts against the request's latency,
     # which is measured from its scheduled arrival)
     ring = 8
-    outs, owner = {}, {}
+    outs = {}
     for i, op in enumerate(ops):
         for adj in (0, 1):
             n = op.Nm if adj else op.Nd
             outs[i, adj] = [torch.empty((32, op.Nt, n), dtype=torch.float64, device=dev) for _ in range(ring)]
-    counters = {key: 0 for key in outs}
-    tickets, keep, t_sub = [], {}, np.empty(len(arrivals))
-    sample = set(range(0, len(arrivals), max(1, len(arrivals) // 8)))
-    t0 = time.perf_counter()
-    for i, (ta, k, a, nr) in enumerate(zip(arrivals, kinds, dirs, nrhs)):
-        key = (int(k), int(a))
-        slot = counters[key] % ring
-        counters[key] += 1
-        prev = owner.get((key, slot))
-        if prev is not None:
-            srv.wait(prev, timeout=120)
-        while time.perf_counter() - t0 < ta:
-            pass
-        x = pools[key][i % 2][: int(nr)]
-        y = outs[key][slot][: int(nr)]
-        t_sub[i] = time.perf_counter() - t0
-        t, _ = srv.submit(ops[key[0]], x, adjoint=bool(a), out=y)
-        owner[(key, slot)] = t
-        tickets.append(t)
-        if i in sample and key[0] in (0, 1):
+
+    def run(rate, seconds, stream, keep_samples):
+        rng = np.random.default_rng(seed_for(5, stream))
+        total = warmup + seconds
+        n_req = int(rate * total * 1.2) + 16
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        arrivals = arrivals[arrivals < total]
+        kinds = rng.integers(0, len(ops), len(arrivals))
+        dirs = rng.integers(0, 2, len(arrivals))
+        nrhs = rng.integers(1, 33, len(arrivals))
+        srv = Server(workspace_budget=budget, n_slots=4, max_batch_rhs=64)
+        owner = {}
+        counters = {key: 0 for key in outs}
+        tickets, keep, t_sub = [], {}, np.empty(len(arrivals))
+        sample = set(range(0, len(arrivals), max(1, len(arrivals) // 8))) if keep_samples else set()
+        t0 = time.perf_counter()
+        for i, (ta, k, a, nr) in enumerate(zip(arrivals, kinds, dirs, nrhs)):
+            key = (int(k), int(a))
+            slot = counters[key] % ring
+            counters[key] += 1
+            prev = owner.get((key, slot))
+            if prev is not None:
+                srv.wait(prev, timeout=120)
+            while time.perf_counter() - t0 < ta:
+                pass
+            x = pools[key][i % 2][: int(nr)]
+            y = outs[key][slot][: int(nr)]
+            t_sub[i] = time.perf_counter() - t0
+            t, _ = srv.submit(ops[key[0]], x, adjoint=bool(a), out=y)
+            owner[(key, slot)] = t
+            tickets.append(t)
+            if i in sample and key[0] in (0, 1):
+                srv.wait(t, timeout=120)
+                keep[i] = (t, y.clone(), k, a, nr)
+        for t in tickets:
             srv.wait(t, timeout=120)
-            keep[i] = (t, y.clone())
-    for t in tickets:
-        srv.wait(t, timeout=120)
-    t_end = time.perf_counter() - t0
-    lat = srv.latencies(tickets[0], len(tickets))
-    lag = t_sub - arrivals                      # client-side delay before submit
-    st = srv.stats()
-    measured = arrivals >= warmup
-    lm = lat[measured] * 1e3
-    la = (lat + lag)[measured] * 1e3            # from the scheduled arrival
-    n_meas = int(measured.sum())
-    vec = int(nrhs[measured].sum())
-    out = {"workload": "4 FP32 operators (Nt,Nd,Nm) = " + ", ".join(f"({s.Nt},{s.Nd},{s.Nm})" for s in SERVING_OPS)
-                       + f"; Poisson {rate:g} req/s; forward/adjoint 50/50; 1-32 vectors uniform; {seconds:g} s "
-                       + f"measured after {warmup:g} s warm-up",
-           "requests": n_meas, "p50_ms": round(float(np.percentile(la, 50)), 3),
-           "p99_ms": round(float(np.percentile(la, 99)), 3), "mean_ms": round(float(la.mean()), 3),
-           "server_p50_ms": round(float(np.percentile(lm, 50)), 3),
-           "server_p99_ms": round(float(np.percentile(lm, 99)), 3),
-           "throughput_req_s": round(n_meas / max(t_end - warmup, 1e-9), 1),
-           "vectors_s": round(vec / max(t_end - warmup, 1e-9), 1),
-           "offered_req_s": rate, "wall_s": round(t_end, 2), "max_submit_lag_ms": round(float(lag.max() * 1e3), 3),
-           "workspace_budget_bytes": budget, "stats": st}
+        t_end = time.perf_counter() - t0
+        lat = srv.latencies(tickets[0], len(tickets))
+        lag = t_sub - arrivals                      # client-side delay before submit
+        st = srv.stats()
+        measured = arrivals >= warmup
+        lm = lat[measured] * 1e3
+        la = (lat + lag)[measured] * 1e3            # from the scheduled arrival
+        n_meas = int(measured.sum())
+        vec = int(nrhs[measured].sum())
+        rec = {"workload": "4 FP32 operators (Nt,Nd,Nm) = " + ", ".join(f"({s.Nt},{s.Nd},{s.Nm})" for s in SERVING_OPS)
+                           + f"; Poisson {rate:g} req/s; forward/adjoint 50/50; 1-32 vectors uniform; {seconds:g} s "
+                           + f"measured after {warmup:g} s warm-up",
+               "requests": n_meas, "p50_ms": round(float(np.percentile(la, 50)), 3),
+               "p99_ms": round(float(np.percentile(la, 99)), 3), "mean_ms": round(float(la.mean()), 3),
+               "server_p50_ms": round(float(np.percentile(lm, 50)), 3),
+               "server_p99_ms": round(float(np.percentile(lm, 99)), 3),
+               "throughput_req_s": round(n_meas / max(t_end - warmup, 1e-9), 1),
+               "vectors_s": round(vec / max(t_end - warmup, 1e-9), 1),
+               "offered_req_s": round(rate, 1), "wall_s": round(t_end, 2),
+               "max_submit_lag_ms": round(float(lag.max() * 1e3), 3),
+               "workspace_budget_bytes": budget, "stats": st}
+        return rec, srv, keep
+
+    out, srv, keep = run(rate, seconds, 4, True)
     # the same request alone on an idle server equals its result in the mix
     diffs = []
-    for i, (t, y) in keep.items():
-        k, a, nr = int(kinds[i]), int(dirs[i]), int(nrhs[i])
+    for i, (t, y, k, a, nr) in keep.items():
+        k, a, nr = int(k), int(a), int(nr)
         x = pools[k, a][i % 2][:nr]
         t2, y2 = srv.submit(ops[k], x, adjoint=bool(a))
         srv.wait(t2, timeout=60)
@@ -270,6 +279,12 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
                       "mix_vs_oracle": float(f"{oracle.relative_l2(y.cpu().numpy(), ref):.3e}")})
     out["sampled_checks"] = diffs
     srv.close()
+    # the same mix offered below the capacity just measured: latency without
+    # the unbounded queueing of an overloaded server
+    below, srv2, _ = run(max(50.0, 0.75 * out["throughput_req_s"]), max(2.0, seconds / 2), 6, False)
+    srv2.close()
+    out["below_capacity"] = {k: v for k, v in below.items() if k != "workspace_budget_bytes"}
+    log("serving below capacity: " + json.dumps({k: v for k, v in below.items() if k != "stats"}))
     for op in ops:
         op.close()
     log("serving: " + json.dumps({k: v for k, v in out.items() if k not in ("sampled_checks", "stats")}))
