@@ -237,6 +237,31 @@ ftm_status ftm_server_get_stats(ftm_server s, ftm_server_stats* out);
 /* Drain every queued and running request, then release the server. */
 ftm_status ftm_server_destroy(ftm_server s);
 
+/* ---- strided-batched matrix-vector product ------------------------------
+ * The standalone form of the phase-3 product (Section 3.1.1): for b < batch,
+ *   y_b = alpha op(A_b) x_b + beta y_b
+ * with BLAS semantics -- A_b is m x n column-major (element (i, j) at
+ * A[b * stride_a + i + j * lda], lda >= max(m, 1)), x_b and y_b are
+ * contiguous (unit increment) at x + b * stride_x and y + b * stride_y.
+ * op = FTM_OP_N: x_b has n entries and y_b m; op = FTM_OP_T (transpose) or
+ * FTM_OP_C (conjugate transpose; the same as T for real types): x_b has m
+ * entries and y_b n.  type selects float, double, complex float or complex
+ * double (complex numbers interleaved re, im); alpha and beta point to one
+ * host value of that type.  y_b is not read when beta is zero.  Tuned for
+ * short-wide matrices (m <= n), where op = T / C tiles the columns of every
+ * matrix across workgroups.  Pointers A, x, y are device memory that the
+ * caller owns; the batch's y_b must not overlap A or x.  Enqueued on stream
+ * (a hipStream_t, NULL = default stream); nothing is allocated.
+ * FTM_ERR_INVALID: bad type or op, NULL pointers, m, n or batch < 1 (with
+ * m, n, batch = 0 the call does nothing and returns FTM_OK), lda < m, m or
+ * n >= 2^31, strides too small for the matrices/vectors they separate
+ * (negative strides included), or more than 2^31 workgroups. */
+typedef enum ftm_gemv_type { FTM_TYPE_S = 0, FTM_TYPE_D = 1, FTM_TYPE_C = 2, FTM_TYPE_Z = 3 } ftm_gemv_type;
+typedef enum ftm_gemv_op { FTM_OP_N = 0, FTM_OP_T = 1, FTM_OP_C = 2 } ftm_gemv_op;
+ftm_status ftm_sbgemv(int32_t type, int32_t op, int64_t m, int64_t n, const void* alpha, const void* A, int64_t lda,
+                      int64_t stride_a, const void* x, int64_t stride_x, const void* beta, void* y, int64_t stride_y,
+                      int64_t batch, void* stream);
+
 const char* ftm_status_string(ftm_status s);
 const char* ftm_last_error(void);
 

@@ -19,6 +19,9 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_BUDGET, ERR_HIP, ERR_STATE = rang
 F64, F32, F16, BF16 = range(4)
 # ftm_rhs_mode
 RHS_AUTO, RHS_GEMV, RHS_GEMM = range(3)
+# ftm_gemv_type, ftm_gemv_op
+TYPE_S, TYPE_D, TYPE_C, TYPE_Z = range(4)
+OP_N, OP_T, OP_C = range(3)
 
 # Every symbol include/ftm.h declares.
 EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
@@ -27,7 +30,7 @@ EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec
            "ftm_set_tuning", "ftm_graph_create", "ftm_graph_launch", "ftm_graph_destroy",
            "ftm_server_create", "ftm_server_submit", "ftm_server_poll", "ftm_server_wait",
            "ftm_server_latencies", "ftm_server_get_stats", "ftm_server_destroy",
-           "ftm_destroy_operator",
+           "ftm_destroy_operator", "ftm_sbgemv",
            "ftm_status_string", "ftm_last_error")
 
 
@@ -91,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "ftm_server_latencies": [vp, ctypes.c_uint64, i64, ctypes.POINTER(ctypes.c_double)],
         "ftm_server_get_stats": [vp, ctypes.POINTER(FtmServerStats)],
         "ftm_server_destroy": [vp],
+        "ftm_sbgemv": [i32, i32, i64, i64, vp, vp, i64, i64, vp, i64, vp, vp, i64, i64, vp],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)

@@ -11,7 +11,7 @@ import dataclasses
 import torch
 
 from . import _lib
-from ._lib import BF16, F16, F32, F64, FtmPrecision, check, lib
+from ._lib import BF16, F16, F32, F64, OP_C, OP_N, OP_T, TYPE_C, TYPE_D, TYPE_S, TYPE_Z, FtmPrecision, check, lib
 
 _CODE = {"d": F64, "s": F32, "h": F16, "b": BF16}
 _CHAR = {v: k for k, v in _CODE.items()}
@@ -369,3 +369,48 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+_SB_TYPES = {torch.float32: (TYPE_S, ctypes.c_float, 1), torch.float64: (TYPE_D, ctypes.c_double, 1),
+             torch.complex64: (TYPE_C, ctypes.c_float, 2), torch.complex128: (TYPE_Z, ctypes.c_double, 2)}
+_SB_OPS = {"N": OP_N, "T": OP_T, "C": OP_C}
+
+
+def sbgemv(A: torch.Tensor, x: torch.Tensor, m: int | None = None, op: str = "N", alpha=1.0, beta=0.0,
+           y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Strided-batched y_b = alpha op(A_b) x_b + beta y_b (``ftm_sbgemv``), BLAS
+    column-major semantics.  ``A`` is a CUDA tensor of shape (batch, n, lda)
+    whose row j holds column j of the m x n matrix A_b (m = lda unless given);
+    ``x`` is (batch, n) for op "N" and (batch, m) for "T" / "C"; ``y`` (batch,
+    m) or (batch, n) is written in place (allocated when None, then beta must
+    be zero).  dtype float32, float64, complex64 or complex128, all the same."""
+    if op not in _SB_OPS:
+        raise ValueError("op must be 'N', 'T' or 'C'")
+    if A.dtype not in _SB_TYPES or x.dtype != A.dtype or (y is not None and y.dtype != A.dtype):
+        raise ValueError("A, x and y must share one of float32, float64, complex64, complex128")
+    if A.dim() != 3 or x.dim() != 2 or not A.is_cuda or not x.is_cuda:
+        raise ValueError("A must be a CUDA (batch, n, lda) tensor and x a CUDA (batch, len) tensor")
+    if not A.is_contiguous() or not x.is_contiguous():
+        raise ValueError("A and x must be contiguous")
+    batch, n, lda = A.shape
+    m = lda if m is None else int(m)
+    nx, ny = (n, m) if op == "N" else (m, n)
+    if tuple(x.shape) != (batch, nx):
+        raise ValueError(f"x must have shape {(batch, nx)}")
+    if y is None:
+        if beta != 0:
+            raise ValueError("beta must be zero when y is allocated here")
+        y = torch.empty((batch, ny), dtype=A.dtype, device=A.device)
+    elif tuple(y.shape) != (batch, ny) or not y.is_contiguous():
+        raise ValueError(f"y must be a contiguous tensor of shape {(batch, ny)}")
+    code, ctype, ncomp = _SB_TYPES[A.dtype]
+
+    def scalar(v):
+        v = complex(v)
+        return (ctype * 2)(v.real, v.imag) if ncomp == 2 else (ctype * 1)(v.real)
+    al, be = scalar(alpha), scalar(beta)
+    with torch.cuda.device(A.device):
+        check(lib().ftm_sbgemv(code, _SB_OPS[op], m, n, ctypes.cast(al, ctypes.c_void_p), A.data_ptr(), lda,
+                               n * lda, x.data_ptr(), nx, ctypes.cast(be, ctypes.c_void_p), y.data_ptr(), ny,
+                               batch, _stream_ptr(stream)), "ftm_sbgemv")
+    return y

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libftm.so")
-SOURCES = ("ftm_api.hip", "ftm_fft.hip", "ftm_gemv.hip", "ftm_gemm.hip", "ftm_server.hip")
+SOURCES = ("ftm_api.hip", "ftm_fft.hip", "ftm_gemv.hip", "ftm_gemm.hip", "ftm_server.hip", "ftm_sbgemv.hip")
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are switched off for every device compile; hipcc's

@@ -316,6 +316,33 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io,
 
 extern "C" {
 
+ftm_status ftm_sbgemv(int32_t type, int32_t op, int64_t m, int64_t n, const void* alpha, const void* A, int64_t lda,
+                      int64_t stride_a, const void* x, int64_t stride_x, const void* beta, void* y, int64_t stride_y,
+                      int64_t batch, void* stream) {
+  try {
+    if (type < FTM_TYPE_S || type > FTM_TYPE_Z) return fail(FTM_ERR_INVALID, "type must be FTM_TYPE_S/D/C/Z");
+    if (op < FTM_OP_N || op > FTM_OP_C) return fail(FTM_ERR_INVALID, "op must be FTM_OP_N/T/C");
+    if (m < 0 || n < 0 || batch < 0) return fail(FTM_ERR_INVALID, "m, n and batch must be >= 0");
+    if (m == 0 || n == 0 || batch == 0) return FTM_OK;
+    if (!alpha || !beta || !A || !x || !y) return fail(FTM_ERR_INVALID, "NULL argument");
+    if (m >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31)) return fail(FTM_ERR_INVALID, "m and n must be < 2^31");
+    if (lda < m) return fail(FTM_ERR_INVALID, "lda must be >= m");
+    const int64_t nx = op == FTM_OP_N ? n : m, ny = op == FTM_OP_N ? m : n;
+    const int64_t a_span = lda * (n - 1) + m;
+    if (batch > 1 && (stride_a < a_span || stride_x < nx || stride_y < ny))
+      return fail(FTM_ERR_INVALID, "strides must separate the batch's matrices and vectors");
+    // workgroups: op N tiles 64 * (16 / element size) rows, op T / C 64 columns
+    const int64_t esz = type == FTM_TYPE_S ? 4 : (type == FTM_TYPE_Z ? 16 : 8);
+    const int64_t per = op == FTM_OP_N ? (m + 64 * (16 / esz) - 1) / (64 * (16 / esz)) : (n + 63) / 64;
+    if (batch > ((int64_t)1 << 31) / per) return fail(FTM_ERR_INVALID, "too many workgroups (batch too large)");
+    FTM_HIP(launch_sbgemv(type, op, (int)m, (int)n, alpha, A, lda, stride_a, x, stride_x, beta, y, stride_y, batch,
+                          reinterpret_cast<hipStream_t>(stream)));
+    return FTM_OK;
+  } catch (...) {
+    return fail(FTM_ERR_INVALID, "internal error");
+  }
+}
+
 const char* ftm_status_string(ftm_status s) {
   switch (s) {
     case FTM_OK: return "ok";

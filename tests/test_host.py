@@ -109,3 +109,27 @@ def test_server_rejects_bad_arguments_without_a_gpu(L):
     done = ctypes.c_int32()
     assert L.ftm_server_poll(None, 1, ctypes.byref(done), None) == ERR_INVALID
     assert L.ftm_server_destroy(None) == 0
+
+
+def test_sbgemv_rejects_bad_arguments_without_a_gpu(L):
+    from paper_2508_10202_amd._lib import ERR_INVALID, OK
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation (or does nothing)
+    one = ctypes.c_double(1.0)
+    a = ctypes.cast(ctypes.pointer(one), ctypes.c_void_p)
+
+    def call(type_=1, op=1, m=4, n=8, lda=4, sa=32, sx=4, sy=8, batch=2, alpha=a, A=fake, x=fake, y=fake):
+        return L.ftm_sbgemv(type_, op, m, n, alpha, A, lda, sa, x, sx, a, y, sy, batch, None)
+
+    assert call(type_=4) == ERR_INVALID
+    assert call(op=3) == ERR_INVALID
+    assert call(m=-1) == ERR_INVALID
+    assert call(A=None) == ERR_INVALID
+    assert call(alpha=None) == ERR_INVALID
+    assert call(lda=3) == ERR_INVALID                       # lda < m
+    assert call(sa=31) == ERR_INVALID                       # matrices overlap
+    assert call(sx=3) == ERR_INVALID                        # op T reads m = 4 entries of x
+    assert call(op=0, sx=4, sy=4) == ERR_INVALID            # op N reads n = 8 entries of x
+    assert call(sy=7) == ERR_INVALID
+    assert call(m=1 << 31, lda=1 << 31) == ERR_INVALID
+    assert call(m=0) == OK and call(n=0) == OK and call(batch=0) == OK
+    assert call(batch=1, sa=0, sx=0, sy=0, A=None) == ERR_INVALID
