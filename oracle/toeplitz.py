@@ -143,8 +143,9 @@ def spectrum(F: np.ndarray, L: int | None = None, ks=None) -> np.ndarray:
 
 def relative_l2(y: np.ndarray, ref: np.ndarray) -> float:
     """``||y - ref||_2 / ||ref||_2`` over the whole output (the paper's relative error)."""
-    y = np.asarray(y, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    cplx = np.iscomplexobj(y) or np.iscomplexobj(ref)
+    y = np.asarray(y, dtype=np.complex128 if cplx else np.float64)
+    ref = np.asarray(ref, dtype=np.complex128 if cplx else np.float64)
     den = float(np.linalg.norm(ref.ravel()))
     num = float(np.linalg.norm((y - ref).ravel()))
     return num / den if den > 0 else num

@@ -95,3 +95,9 @@ def test_single_entry_matrix():
     yn, yt = oracle.sbgemv("N", _cols(M), m, xn), oracle.sbgemv("T", _cols(M), m, xm)
     assert yn[0, i] == xn[0, j] and np.count_nonzero(yn) == 1
     assert yt[0, j] == xm[0, i] and np.count_nonzero(yt) == 1
+
+
+def test_relative_l2_counts_imaginary_parts():
+    # ||(1+i) - 1|| / ||1|| = 1: an error only in the imaginary part is seen
+    assert oracle.relative_l2(np.array([1 + 1j]), np.array([1 + 0j])) == 1.0
+    assert oracle.relative_l2(np.array([3.0, 4.0]), np.array([0.0, 4.0])) == 0.75
