@@ -16,6 +16,9 @@ Besides the JSON fields of the benchmark contract the line carries:
   rel_err       float64 relative L2 error of both directions vs the oracle
   mixed         per-phase mixed precision: time and error per configuration,
                 the Pareto front and the fastest configuration under each tolerance
+  multi_rhs     64 right-hand sides through the matrix-core products
+  serving       the continuous-batching server under Poisson load
+  sbgemv        the standalone strided-batched product at short-wide shapes
 """
 from __future__ import annotations
 
@@ -161,6 +164,53 @@ def multi_rhs_section(log):
         log(f"multi-rhs {prec}: " + json.dumps(rec))
     op.close()
     return out
+
+
+def sbgemv_section(log):
+    """The standalone strided-batched product at the shapes of the paper's
+    kernel benchmark (Section 4.1.1): batch 100, short-wide m x n matrices
+    with n = 4096 and m from 32 to 4096, transposed for real types and
+    conjugate-transposed for complex ones; also op N at m = 128.  GB/s counts
+    the matrices, x and y once; sampled batch entries are checked against the
+    oracle at m = 128."""
+    import torch
+
+    import oracle
+    from paper_2508_10202_amd import sbgemv
+    dev = torch.device("cuda:0")
+    types = (("s", torch.float32, "T"), ("d", torch.float64, "T"), ("c", torch.complex64, "C"),
+             ("z", torch.complex128, "C"))
+    batch, n = 100, 4096
+    g = torch.Generator(device=dev).manual_seed(2508_10202 + 600)
+    rows = []
+    for t, dt, op0 in types:
+        for m, op in ((32, op0), (128, op0), (1024, op0), (4096, op0), (128, "N")):
+            A = torch.randn((batch, n, m), dtype=dt, device=dev, generator=g)
+            nx, ny = (n, m) if op == "N" else (m, n)
+            x = torch.randn((batch, nx), dtype=dt, device=dev, generator=g)
+            y = torch.empty((batch, ny), dtype=dt, device=dev)
+            for _ in range(3):
+                sbgemv(A, x, op=op, y=y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                sbgemv(A, x, op=op, y=y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = batch * (m * n + m + n) * A.element_size()
+            row = {"type": t, "op": op, "m": m, "n": n, "batch": batch, "ms": round(ms, 4),
+                   "gbs": round(nbytes / ms / 1e6, 1), "frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 3)}
+            if m == 128:
+                pick = [0, 99]
+                ref = oracle.sbgemv(op, A[pick].cpu().numpy(), m, x[pick].cpu().numpy())
+                row["rel_err"] = float(f"{oracle.relative_l2(y[pick].cpu().numpy(), ref):.3e}")
+            rows.append(row)
+            del A, x, y
+    torch.cuda.empty_cache()
+    log("sbgemv: " + json.dumps(rows))
+    return rows
 
 
 def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000.0):
@@ -434,6 +484,7 @@ def main() -> int:
         log("mixed best: " + json.dumps(mixed["best"]))
 
     multi = None if args.no_multi_rhs else multi_rhs_section(log)
+    sbg = None if args.no_multi_rhs else sbgemv_section(log)
     serving = None
     if args.serving_seconds > 0:
         op.close()
@@ -455,7 +506,7 @@ def main() -> int:
         "hbm_gbs": {"fwd": round(matvec_bytes(s, 16) / (fwd_ms * 1e-3) / 1e9, 1),
                     "adj": round(matvec_bytes(s, 16) / (adj_ms * 1e-3) / 1e9, 1)},
         "kernels_ms": kms, "rel_err": rel, "roofline": roofline, "cpu_baseline": cpu_baseline,
-        "mixed": mixed, "multi_rhs": multi, "serving": serving,
+        "mixed": mixed, "multi_rhs": multi, "serving": serving, "sbgemv": sbg,
     }
     op.close()
     if args.copy_calibration_gib > 0:
@@ -473,6 +524,8 @@ def main() -> int:
     short = dict(rec)
     if mixed:
         short["mixed"] = {"best": mixed["best"], "pareto": mixed["pareto"]}
+    if sbg:
+        short["sbgemv"] = {f'{r["type"]}{r["op"]} m={r["m"]}': {"gbs": r["gbs"], "frac": r["frac"]} for r in sbg}
     print(json.dumps(short), flush=True)
     return 0
 

@@ -86,7 +86,7 @@ constexpr int SB_TILE = 64;      // columns per workgroup (transposed kernels)
 // ---- op = T / C ---------------------------------------------------------------
 // V elements per 16-byte load (1 when lda or a pointer does not allow it), G
 // lanes per column.
-template <class T, int V, int G, bool CJ>
+template <class T, int V, int G, bool CJ, int CPG = 4>
 __global__ __launch_bounds__(SB_THREADS) void sbgemv_t_kernel(int m, int n, T alpha, const T* __restrict__ A,
                                                                int64_t lda, int64_t sa, const T* __restrict__ x,
                                                                int64_t sx, T beta, T* __restrict__ y, int64_t sy,
@@ -100,23 +100,42 @@ __global__ __launch_bounds__(SB_THREADS) void sbgemv_t_kernel(int m, int n, T al
   const T* __restrict__ Ab = A + b * sa;
   const T* __restrict__ xb = x + b * sx;
   const int nchunk = (m + V - 1) / V;
-  for (int c = tile * SB_TILE + g; c < min(n, (tile + 1) * SB_TILE); c += NG) {
-    const T* __restrict__ col = Ab + (int64_t)c * lda;
-    typename E::acc s = E::zero();
+  const int cend = min(n, (tile + 1) * SB_TILE);
+  // CPG columns per group at a time, so that each lane has CPG loads in flight
+  for (int c0 = tile * SB_TILE + g; c0 < cend; c0 += NG * CPG) {
+    typename E::acc s[CPG];
+    const T* __restrict__ col[CPG];
+#pragma unroll
+    for (int u = 0; u < CPG; ++u) {
+      s[u] = E::zero();
+      col[u] = Ab + (int64_t)min(c0 + u * NG, cend - 1) * lda;  // clamped columns are not stored
+    }
     for (int q = li; q < nchunk; q += G) {
       const int i0 = q * V;
       if (V > 1 && i0 + V <= m) {
-        const Vec<T, V> a = *reinterpret_cast<const Vec<T, V>*>(col + i0);
         const Vec<T, V> xv = *reinterpret_cast<const Vec<T, V>*>(xb + i0);
+        Vec<T, V> a[CPG];
 #pragma unroll
-        for (int v = 0; v < V; ++v) s = E::mac(s, a.e[v], xv.e[v], CJ);
+        for (int u = 0; u < CPG; ++u) a[u] = *reinterpret_cast<const Vec<T, V>*>(col[u] + i0);
+#pragma unroll
+        for (int u = 0; u < CPG; ++u)
+#pragma unroll
+          for (int v = 0; v < V; ++v) s[u] = E::mac(s[u], a[u].e[v], xv.e[v], CJ);
       } else {
-        for (int v = 0; v < V && i0 + v < m; ++v) s = E::mac(s, col[i0 + v], xb[i0 + v], CJ);
+        for (int v = 0; v < V && i0 + v < m; ++v) {
+          const T xi = xb[i0 + v];
+#pragma unroll
+          for (int u = 0; u < CPG; ++u) s[u] = E::mac(s[u], col[u][i0 + v], xi, CJ);
+        }
       }
     }
 #pragma unroll
-    for (int d = G / 2; d > 0; d >>= 1) s = E::add(s, E::shfl_xor(s, d));
-    if (li == 0) finish(y + b * sy + c, s, alpha, beta);
+    for (int u = 0; u < CPG; ++u) {
+#pragma unroll
+      for (int d = G / 2; d > 0; d >>= 1) s[u] = E::add(s[u], E::shfl_xor(s[u], d));
+      const int c = c0 + u * NG;
+      if (li == 0 && c < cend) finish(y + b * sy + c, s[u], alpha, beta);
+    }
   }
 }
 
