@@ -193,6 +193,9 @@ def sbgemv_section(log):
                 sbgemv(A, x, op=op, y=y)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             reps = 20
+            # keep the GPU busy while the host enqueues the timed launches, so
+            # that host-side call overhead never leaves the GPU idle between them
+            torch.cuda._sleep(5_000_000)
             e0.record()
             for _ in range(reps):
                 sbgemv(A, x, op=op, y=y)
