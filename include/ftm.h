@@ -88,8 +88,11 @@ typedef struct ftm_operator_s* ftm_operator;
  *            always kept.
  *   max_rhs  largest nrhs later passed to matvec/rmatvec (>= 1); sizes the
  *            workspace.
- * Limits: Nt in [1, 2048], Nd, Nm >= 1.  The pad length is L = 2 Nt.
- * Returns FTM_ERR_UNSUPPORTED if L has a prime factor above 7. */
+ * Limits: Nt in [1, 2048], Nd, Nm >= 1.  The pad length L is 2 Nt when 2 Nt
+ * has no prime factor above 7, else the next even length that has none (any
+ * L >= 2 Nt - 1 gives the same product); K = L / 2 + 1 frequencies are
+ * kept (ftm_operator_info reports L).  FTM_ERR_UNSUPPORTED when that length
+ * exceeds 4096. */
 ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd,
                               int64_t Nm, const ftm_precision* fwd, const ftm_precision* adj,
                               uint32_t spectra, int64_t max_rhs, void* stream);

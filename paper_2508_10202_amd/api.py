@@ -108,6 +108,10 @@ class Operator:
                                        self.max_rhs, st), "ftm_setup_operator")
         self._h = h
         self.fwd, self.adj = fwd, adj
+        Lc = ctypes.c_int64()
+        check(L.ftm_operator_info(h, None, None, None, ctypes.byref(Lc), None), "ftm_operator_info")
+        self.L = int(Lc.value)           # pad length (2 Nt, or the next 7-smooth even length)
+        self.K = self.L // 2 + 1         # kept frequencies
 
     # -- properties -------------------------------------------------------------
     @property
@@ -159,7 +163,7 @@ class Operator:
 
     def spectrum(self, which="d", k0: int = 0, nk: int | None = None, stream=None) -> torch.Tensor:
         """Stored ``Fhat_k`` for ``k0 <= k < k0 + nk`` as complex128 ``[nk, Nd, Nm]``."""
-        nk = (self.Nt + 1 - k0) if nk is None else nk
+        nk = (self.K - k0) if nk is None else nk
         code = _CODE[which] if isinstance(which, str) else int(which)
         out = torch.empty((nk, self.Nd, self.Nm, 2), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):

@@ -367,8 +367,19 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     if (!F) return fail(FTM_ERR_INVALID, "F is NULL");
     if (Nt < 1 || Nd < 1 || Nm < 1 || max_rhs < 1)
       return fail(FTM_ERR_INVALID, "Nt, Nd, Nm and max_rhs must be >= 1");
-    if (2 * Nt > FFT_POINTS)
-      return fail(FTM_ERR_UNSUPPORTED, "Nt above " + std::to_string(FFT_POINTS / 2) + " is not supported");
+    // pad length: 2 Nt when it factors into 2, 3, 5 and 7 (the paper's
+    // choice), else the next even length that does -- circular and linear
+    // convolution agree on the first Nt outputs for any L >= 2 Nt - 1
+    int64_t L = 2 * Nt;
+    auto smooth = [](int64_t v) {
+      for (int64_t r : {2, 3, 5, 7})
+        while (v % r == 0) v /= r;
+      return v == 1;
+    };
+    while (L <= FFT_POINTS && !smooth(L)) L += 2;
+    if (L > FFT_POINTS)
+      return fail(FTM_ERR_UNSUPPORTED, "no transform length of at most " + std::to_string(FFT_POINTS) +
+                                           " covers Nt = " + std::to_string(Nt));
     if (Nd > (1 << 24) || Nm > (1 << 24) || Nd * Nm > ((int64_t)1 << 34) || max_rhs > (1 << 20))
       return fail(FTM_ERR_UNSUPPORTED, "size too large");
     if (spectra >> 4) return fail(FTM_ERR_INVALID, "spectra mask has bits beyond FTM_BF16");
@@ -377,15 +388,15 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
 
     FftPlan plan{}, plan32{};
-    if (!make_plan((int)(2 * Nt), 3, &plan) || !make_plan((int)(2 * Nt), FTM_FFT_RADIX16 ? 4 : 3, &plan32))
-      return fail(FTM_ERR_UNSUPPORTED, "2*Nt must factor into 2, 3, 5 and 7");
+    if (!make_plan((int)L, 3, &plan) || !make_plan((int)L, FTM_FFT_RADIX16 ? 4 : 3, &plan32))
+      return fail(FTM_ERR_UNSUPPORTED, "no FFT plan for L = " + std::to_string(L));
 
     ftm_operator op = new ftm_operator_s();
     op->Nt = Nt;
     op->Nd = Nd;
     op->Nm = Nm;
-    op->L = 2 * Nt;
-    op->K = Nt + 1;
+    op->L = L;
+    op->K = L / 2 + 1;
     op->ldm = (int)((Nm + 7) / 8 * 8);
     op->ldd = (int)((Nd + 7) / 8 * 8);
     op->max_rhs = max_rhs;

@@ -27,11 +27,21 @@ def _rel(a, b):
     return oracle.relative_l2(a, b)
 
 
+def _prime_factors(v):
+    out, p = [], 2
+    while v > 1:
+        while v % p == 0:
+            out.append(p)
+            v //= p
+        p += 1
+    return out
+
+
 def _run(F, m=None, d=None, **kw):
     import torch
     from paper_2508_10202_amd import Operator
     op = Operator(torch.from_numpy(F).cuda(), **kw)
-    out = {}
+    out = {"L": op.L}
     if m is not None:
         out["d"] = op.matvec(torch.from_numpy(m).cuda()).cpu().numpy()
     if d is not None:
@@ -62,6 +72,11 @@ RAGGED = [
     Shape(2048, 2, 9, decay=500.0),   # largest supported Nt, L = 4096
     Shape(100, 37, 1000),             # L = 200, several column tiles
     Shape(12, 9, 24, scale_by_sqrt_nm=False, decay=None),  # L = 24 = 8*3
+    # 2 Nt with a prime factor above 7: the next 7-smooth even length is used
+    Shape(11, 3, 7, decay=None),      # 2 Nt = 22 -> L = 24
+    Shape(23, 5, 40, decay=10.0),     # 46 -> 48
+    Shape(97, 4, 33, decay=40.0),     # 194 -> 196 = 4*7*7
+    Shape(2047, 2, 5, decay=500.0),   # 4094 -> 4096
 ]
 
 
@@ -70,6 +85,9 @@ def test_ragged_shapes_fp64(gpu, s):
     _say("case ragged", s)
     F, m, d = make_F(s, 11), make_m(s, 12)[0], make_d(s, 13)[0]
     out = _run(F, m, d)
+    assert out["L"] >= 2 * s.Nt and out["L"] % 2 == 0
+    if all(p in (2, 3, 5, 7) for p in _prime_factors(2 * s.Nt)):
+        assert out["L"] == 2 * s.Nt                     # the paper's length whenever it factors
     assert _rel(out["d"], oracle.forward(F, m)) <= FP64_TOL
     assert _rel(out["m"], oracle.adjoint(F, d)) <= FP64_TOL
 

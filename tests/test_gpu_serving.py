@@ -121,7 +121,7 @@ def test_tiny_budget_queues_instead_of_failing(gpu, ops):
 
 def _ws(op, nrhs):
     """Workspace bytes of one batch, as the library sizes it."""
-    K = op.Nt + 1
+    K = op.K
     ldm, ldd = (op.Nm + 7) // 8 * 8, (op.Nd + 7) // 8 * 8
     return K * nrhs * (ldm + ldd) * 16 + 512 + 512
 
@@ -129,7 +129,7 @@ def _ws(op, nrhs):
 def _ws32(op, nrhs):
     """Workspace bytes of one batch whose transformed vectors are float32 (the
     library's sizing, rounded to the arena's 256-byte grain)."""
-    K = op.Nt + 1
+    K = op.K
     ldm, ldd = (op.Nm + 7) // 8 * 8, (op.Nd + 7) // 8 * 8
     m = (K * nrhs * ldm * 8 + 255) // 256 * 256
     return (m + K * nrhs * ldd * 8 + 512 + 255) // 256 * 256

@@ -57,8 +57,8 @@ def test_setup_rejects_bad_arguments_without_a_gpu(L):
     assert _setup(L, ctypes.byref(h), fake, 4, 0, 3) == ERR_INVALID
     assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, max_rhs=0) == ERR_INVALID
     assert b"max_rhs" in L.ftm_last_error()
-    # 2*Nt = 22 has the prime factor 11
-    assert _setup(L, ctypes.byref(h), fake, 11, 2, 3) == ERR_UNSUPPORTED
+    # no transform length of at most 4096 covers Nt above 2048
+    assert _setup(L, ctypes.byref(h), fake, 2049, 2, 3) == ERR_UNSUPPORTED
     assert _setup(L, ctypes.byref(h), fake, 4096, 2, 3) == ERR_UNSUPPORTED
     assert _setup(L, ctypes.byref(h), fake, 4, 2, 3, spectra=1 << 5) == ERR_INVALID
     bad = FtmPrecision(0, 0, 0, 0, 0, 1)      # FP64 product with FP32 accumulation
