@@ -14,6 +14,7 @@
 #include "ftm.h"
 #include "ftm_device.h"
 #include "ftm_kernels.h"
+#include "ftm_sbgemv.h"
 #include "ftm_runtime.h"
 
 using namespace ftm;

@@ -124,10 +124,4 @@ hipError_t launch_store_spectrum(const void* src, int dt, void* dst, int64_t n, 
 hipError_t launch_widen_spectrum(const void* src, int dt, void* dst, int64_t rows, int64_t ncol,
                                  int64_t ld, hipStream_t st);
 
-// Strided-batched matrix-vector product (standalone, BLAS column-major
-// semantics; see ftm_sbgemv in ftm.h).  Arguments are validated by the caller.
-hipError_t launch_sbgemv(int type, int op, int m, int n, const void* alpha, const void* A, int64_t lda, int64_t sa,
-                         const void* x, int64_t sx, const void* beta, void* y, int64_t sy, int64_t batch,
-                         hipStream_t st);
-
 }  // namespace ftm

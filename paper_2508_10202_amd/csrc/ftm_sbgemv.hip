@@ -18,6 +18,7 @@
 #include "ftm.h"
 #include "ftm_device.h"
 #include "ftm_kernels.h"
+#include "ftm_sbgemv.h"
 
 namespace ftm {
 
