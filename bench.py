@@ -192,18 +192,21 @@ def sbgemv_section(log):
             for _ in range(3):
                 sbgemv(A, x, op=op, y=y)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 20
-            # keep the GPU busy while the host enqueues the timed launches, so
-            # that host-side call overhead never leaves the GPU idle between them
-            torch.cuda._sleep(5_000_000)
-            e0.record()
-            for _ in range(reps):
-                sbgemv(A, x, op=op, y=y)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
+            reps, trials = 20, []
+            for _ in range(3):
+                # keep the GPU busy while the host enqueues the timed launches, so
+                # that host-side call overhead never leaves the GPU idle between them
+                torch.cuda._sleep(5_000_000)
+                e0.record()
+                for _ in range(reps):
+                    sbgemv(A, x, op=op, y=y)
+                e1.record()
+                torch.cuda.synchronize()
+                trials.append(e0.elapsed_time(e1) / reps)
+            ms = sorted(trials)[1]                     # median of 3 trials of 20 launches
             nbytes = batch * (m * n + m + n) * A.element_size()
             row = {"type": t, "op": op, "m": m, "n": n, "batch": batch, "ms": round(ms, 4),
+                   "trials_ms": [round(v, 4) for v in trials],
                    "gbs": round(nbytes / ms / 1e6, 1), "frac": round(nbytes / ms / 1e6 / PEAK_HBM_GBS, 3)}
             if m == 128:
                 pick = [0, 99]
