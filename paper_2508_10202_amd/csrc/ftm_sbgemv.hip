@@ -161,6 +161,7 @@ __global__ __launch_bounds__(64 * SBN_WAVES) void sbgemv_n_kernel(int m, int n, 
   for (int v = 0; v < V; ++v) s[v] = E::zero();
   if (i0 < m) {
     const bool full = i0 + V <= m;
+#pragma unroll 8
     for (int j = w; j < n; j += SBN_WAVES) {
       const T xj = xb[j];
       const T* __restrict__ cj = Ab + (int64_t)j * lda + i0;
