@@ -332,9 +332,8 @@ ftm_status ftm_sbgemv(int32_t type, int32_t op, int64_t m, int64_t n, const void
     const int64_t a_span = lda * (n - 1) + m;
     if (batch > 1 && (stride_a < a_span || stride_x < nx || stride_y < ny))
       return fail(FTM_ERR_INVALID, "strides must separate the batch's matrices and vectors");
-    // workgroups: op N tiles 64 * (16 / element size) rows, op T / C 64 columns
-    const int64_t esz = type == FTM_TYPE_S ? 4 : (type == FTM_TYPE_Z ? 16 : 8);
-    const int64_t per = op == FTM_OP_N ? (m + 64 * (16 / esz) - 1) / (64 * (16 / esz)) : (n + 63) / 64;
+    // workgroups per matrix: op N tiles at least 64 rows, op T / C 64 columns
+    const int64_t per = op == FTM_OP_N ? (m + 63) / 64 : (n + 63) / 64;
     if (batch > ((int64_t)1 << 31) / per) return fail(FTM_ERR_INVALID, "too many workgroups (batch too large)");
     FTM_HIP(launch_sbgemv(type, op, (int)m, (int)n, alpha, A, lda, stride_a, x, stride_x, beta, y, stride_y, batch,
                           reinterpret_cast<hipStream_t>(stream)));

@@ -76,8 +76,9 @@ __device__ __forceinline__ void finish(T* y, typename El<T>::acc s, T alpha, T b
   *y = r;
 }
 
+// V consecutive elements, loaded as one access of V * sizeof(T) <= 16 bytes
 template <class T, int V>
-struct alignas(16) Vec {
+struct alignas(sizeof(T) * V) Vec {
   T e[V];
 };
 
@@ -234,7 +235,13 @@ hipError_t dispatch(int op, int m, int n, const void* alpha, const void* A, int6
   const bool vec = V > 1 && lda % V == 0 && sa % V == 0 && aligned(A) &&
                    (op == FTM_OP_N || (sx % V == 0 && aligned(x)));
   if (op == FTM_OP_N) {
-    if (vec) return go_n<T, V>(m, n, al, a, lda, sa, xv, sx, be, yv, sy, batch, st);
+    // narrower loads when the row tiles of 64 V rows would leave the chip
+    // with fewer than 2 workgroups per CU (short matrices, small batches)
+    auto wgs = [&](int v) { return batch * ((m + 64 * v - 1) / (64 * v)); };
+    if (vec && (V == 1 || wgs(V) >= 512)) return go_n<T, V>(m, n, al, a, lda, sa, xv, sx, be, yv, sy, batch, st);
+    if constexpr (V == 4) {
+      if (vec && wgs(2) >= 512) return go_n<T, 2>(m, n, al, a, lda, sa, xv, sx, be, yv, sy, batch, st);
+    }
     return go_n<T, 1>(m, n, al, a, lda, sa, xv, sx, be, yv, sy, batch, st);
   }
   const bool cj = op == FTM_OP_C;

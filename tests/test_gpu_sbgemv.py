@@ -95,3 +95,17 @@ def test_paper_kernel_shape_all_types(gpu):
         ref = oracle.sbgemv(op, A.numpy()[pick], m, x.numpy()[pick])
         assert oracle.relative_l2(got[pick], ref) <= _tol(t, m)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("t", list("sdcz"))
+@pytest.mark.parametrize("m,batch", [(256, 300), (512, 600)])
+def test_op_n_load_widths(gpu, t, m, batch):
+    """op N picks 16-, 8- or 4-byte loads from the grid size: batches large
+    enough for the full and the halved width, against the oracle."""
+    from paper_2508_10202_amd import sbgemv
+    n = 40
+    _say("case sbgemv op N widths", t, m, batch)
+    A, x, _ = _inputs(t, batch, m, n, m, "N", 31 + m)
+    got = sbgemv(A.cuda(), x.cuda(), op="N").cpu().numpy()
+    ref = oracle.sbgemv("N", A.numpy(), m, x.numpy())
+    assert oracle.relative_l2(got, ref) <= _tol(t, n)
