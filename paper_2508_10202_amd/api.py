@@ -411,6 +411,8 @@ def sbgemv(A: torch.Tensor, x: torch.Tensor, m: int | None = None, op: str = "N"
 
     def scalar(v):
         v = complex(v)
+        if ncomp == 1 and v.imag != 0:
+            raise ValueError("alpha and beta must be real for real types")
         return (ctype * 2)(v.real, v.imag) if ncomp == 2 else (ctype * 1)(v.real)
     al, be = scalar(alpha), scalar(beta)
     with torch.cuda.device(A.device):
