@@ -133,3 +133,18 @@ def test_sbgemv_rejects_bad_arguments_without_a_gpu(L):
     assert call(m=1 << 31, lda=1 << 31) == ERR_INVALID
     assert call(m=0) == OK and call(n=0) == OK and call(batch=0) == OK
     assert call(batch=1, sa=0, sx=0, sy=0, A=None) == ERR_INVALID
+
+
+def test_binding_constants_match_the_header():
+    from paper_2508_10202_amd import _lib
+    text = open(HEADER).read()
+
+    def enum(name):
+        return int(re.search(r"\b%s\s*=\s*(\d+)" % name, text).group(1))
+    assert (enum("FTM_TYPE_S"), enum("FTM_TYPE_D"), enum("FTM_TYPE_C"), enum("FTM_TYPE_Z")) == \
+        (_lib.TYPE_S, _lib.TYPE_D, _lib.TYPE_C, _lib.TYPE_Z)
+    assert (enum("FTM_OP_N"), enum("FTM_OP_T"), enum("FTM_OP_C")) == (_lib.OP_N, _lib.OP_T, _lib.OP_C)
+    assert (enum("FTM_F64"), enum("FTM_F32"), enum("FTM_F16"), enum("FTM_BF16")) == \
+        (_lib.F64, _lib.F32, _lib.F16, _lib.BF16)
+    assert (enum("FTM_RHS_AUTO"), enum("FTM_RHS_GEMV"), enum("FTM_RHS_GEMM")) == \
+        (_lib.RHS_AUTO, _lib.RHS_GEMV, _lib.RHS_GEMM)
