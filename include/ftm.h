@@ -25,8 +25,14 @@
  *     valid once the stream has been synchronised.
  *   - The library owns the spectra, twiddle tables and workspaces it
  *     allocates; ftm_destroy_operator releases them.
- *   - Concurrent calls on one operator must use one stream (they share the
- *     operator's workspace) unless the serving API below is used.
+ *   - ftm_matvec / ftm_rmatvec use the operator's own workspace: concurrent
+ *     calls on one operator must then be on one stream.  ftm_apply takes a
+ *     workspace from the caller, so calls with different workspaces may run
+ *     concurrently on different streams; so do the serving API's batches.
+ *   - The configuration setters (ftm_set_precision, ftm_set_rhs_mode,
+ *     ftm_set_gemm_crossover, ftm_set_tuning, ftm_profile_enable) may be
+ *     called from any thread: each call copies the configuration it runs
+ *     with, under the operator's lock, when it is made.
  *
  * Errors
  *   - Every entry point returns an ftm_status; nothing throws or aborts
@@ -111,6 +117,30 @@ ftm_status ftm_matvec(ftm_operator op, const double* m, double* d, int64_t nrhs,
  *   d device float64 [nrhs][Nt][Nd];  m device float64 [nrhs][Nt][Nm]. */
 ftm_status ftm_rmatvec(ftm_operator op, const double* d, double* m, int64_t nrhs, void* stream);
 
+/* Bytes of device workspace one call of ftm_apply needs for nrhs right-hand
+ * sides (1 <= nrhs <= 2^20) in the given direction at the operator's current
+ * precision configuration: K * nrhs * (ldm * e_m + ldd * e_d), each part
+ * rounded up to 256 bytes, where e_m and e_d are 16 for a transformed vector
+ * stored in float64 (both neighbouring phases float64) and 8 otherwise, and
+ * ldm, ldd are Nm and Nd rounded up to 8. */
+ftm_status ftm_workspace_size(ftm_operator op, int32_t adjoint, int64_t nrhs, size_t* bytes);
+
+/* y = F x (adjoint = 0) or y = F^T x (adjoint != 0) for nrhs right-hand
+ * sides (1 <= nrhs <= 2^20, not limited by max_rhs), as ftm_matvec /
+ * ftm_rmatvec but on a workspace the caller provides (Section 2.4: the
+ * transformed vectors of phases 2-4 live there).
+ *   x, y       device float64, [nrhs][Nt][Nm] / [nrhs][Nt][Nd] as for
+ *              ftm_matvec (swapped for the adjoint); must not overlap.
+ *   workspace  device memory of at least ftm_workspace_size(op, adjoint,
+ *              nrhs) bytes, 256-byte aligned, not overlapping x or y; its
+ *              contents on entry do not matter and are clobbered.  It is in
+ *              use until the stream reaches the end of the call.
+ * Calls with distinct workspaces may run concurrently on different streams.
+ * FTM_ERR_INVALID: NULL pointers, nrhs out of range, a workspace that is too
+ * small, misaligned or overlapping. */
+ftm_status ftm_apply(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
 /* How phase 3 treats nrhs > 1 right-hand sides:
  *   FTM_RHS_AUTO  (default) matrix-core GEMM when the product's storage is
  *                 FP32/FP16/BF16 with FP32 accumulation and nrhs >= the
@@ -190,14 +220,13 @@ ftm_status ftm_destroy_operator(ftm_operator op);
  * Results are the same, within the precision configuration's tolerance, as
  * a lone ftm_matvec/ftm_rmatvec of the same input (bitwise when the product
  * takes the same path; see ftm_set_rhs_mode).
- * The operators' precision configuration is read when a batch launches, and
- * so is a batch's workspace size: K * nrhs * (ldm * e_m + ldd * e_d) bytes
- * (plus alignment), where e_m and e_d are 16 for a transformed vector stored
- * in float64 (both neighbouring phases float64) and 8 otherwise, ldm and ldd
- * being Nm and Nd rounded up to 8.  A queued request that no longer fits the
- * whole budget at its operator's configuration when it reaches the head of
- * the queue fails (FTM_ERR_HIP from ftm_server_wait / poll, with the reason
- * in ftm_last_error) instead of waiting forever. */
+ * The operators' precision configuration is copied when a batch is
+ * admitted; the batch is sized and runs with that copy.  A batch's workspace
+ * is ftm_workspace_size of its operator, direction and total nrhs.  The
+ * budget is used in 256-byte granules (rounded down).  A queued request that
+ * no longer fits the whole budget at its operator's configuration when it
+ * reaches the head of the queue fails (FTM_ERR_HIP from ftm_server_wait /
+ * poll, with the reason in ftm_last_error) instead of waiting forever. */
 typedef struct ftm_server_s* ftm_server;
 
 typedef struct ftm_server_stats {

@@ -161,6 +161,41 @@ class Operator:
         """``m = F^T d``; ``d`` is ``[Nt, Nd]`` or ``[nrhs, Nt, Nd]``."""
         return self._apply(d, True, out, stream)
 
+    def workspace_size(self, nrhs: int = 1, adjoint: bool = False) -> int:
+        """Workspace bytes one :meth:`apply` call of ``nrhs`` vectors needs at the
+        current precision (``ftm_workspace_size``)."""
+        n = ctypes.c_size_t()
+        check(lib().ftm_workspace_size(self.handle, 1 if adjoint else 0, int(nrhs), ctypes.byref(n)),
+              "ftm_workspace_size")
+        return int(n.value)
+
+    def apply(self, x: torch.Tensor, workspace: torch.Tensor, adjoint: bool = False, out=None,
+              stream=None) -> torch.Tensor:
+        """``F x`` (or ``F^T x``) on a caller-owned workspace (``ftm_apply``):
+        calls with distinct workspaces may run concurrently on different
+        streams.  ``workspace`` is a CUDA tensor of at least
+        :meth:`workspace_size` bytes; ``nrhs`` is not limited by ``max_rhs``."""
+        n_in, n_out = (self.Nd, self.Nm) if adjoint else (self.Nm, self.Nd)
+        x = _dev_f64(x, "x")
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        if xb.dim() != 3 or tuple(xb.shape[1:]) != (self.Nt, n_in):
+            raise ValueError(f"input must be [nrhs,] {self.Nt} x {n_in}, got {tuple(x.shape)}")
+        if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or not workspace.is_contiguous():
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        nrhs = xb.shape[0]
+        if out is None:
+            out = torch.empty((nrhs, self.Nt, n_out), dtype=torch.float64, device=x.device)
+        else:
+            out = _dev_f64(out, "out")
+            if out.numel() != nrhs * self.Nt * n_out:
+                raise ValueError("out has the wrong size")
+        nbytes = workspace.numel() * workspace.element_size()
+        with torch.cuda.device(x.device):
+            check(lib().ftm_apply(self.handle, 1 if adjoint else 0, xb.data_ptr(), out.data_ptr(), nrhs,
+                                  workspace.data_ptr(), nbytes, _stream_ptr(stream)), "ftm_apply")
+        return out[0] if single and out.dim() == 3 else out
+
     def spectrum(self, which="d", k0: int = 0, nk: int | None = None, stream=None) -> torch.Tensor:
         """Stored ``Fhat_k`` for ``k0 <= k < k0 + nk`` as complex128 ``[nk, Nd, Nm]``."""
         nk = (self.K - k0) if nk is None else nk

@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -36,17 +38,29 @@ ftm_status fail_hip(const char* what, hipError_t e) {
   return fail(FTM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs, bool adjoint) {
+Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs, bool adjoint, const ftm_precision& p) {
   int em, ed;
-  op->workspace_elems(adjoint, &em, &ed);
+  ftm_operator_s::workspace_elems(p, adjoint, &em, &ed);
   Workspace w;
-  char* p = reinterpret_cast<char*>(base);
-  w.mhat = p;
-  w.dhat = p + ftm_operator_s::round256((size_t)op->K * nrhs * op->ldm * em);
+  char* b = reinterpret_cast<char*>(base);
+  w.mhat = b;
+  w.dhat = b + ftm_operator_s::round256((size_t)op->K * nrhs * op->ldm * em);
   return w;
 }
 
 }  // namespace ftm_rt
+
+ftm_rt::Exec ftm_operator_s::exec(bool adjoint, int64_t nrhs, bool allow_profile) const {
+  std::lock_guard<std::mutex> lk(mu);
+  ftm_rt::Exec e;
+  e.p = adjoint ? adj : fwd;
+  e.gemv_variant = variant[adjoint ? 1 : 0][e.p.gemv];
+  // many right-hand sides: one pass of the spectrum through the matrix cores
+  const bool gemm_ok = e.p.gemv != ftm::DT_F64 && e.p.accum != ftm::DT_F64 && nrhs >= 2;
+  e.use_gemm = gemm_ok && (rhs_mode == FTM_RHS_GEMM || (rhs_mode == FTM_RHS_AUTO && nrhs >= gemm_min_rhs));
+  e.profile = allow_profile && profiling;
+  return e;
+}
 
 namespace {
 
@@ -193,16 +207,18 @@ ftm_status ensure_spectra(ftm_operator op, uint32_t mask, hipStream_t st) {
   return FTM_OK;
 }
 
-// Record event i of the current profiled call (no-op when not profiling).
+// Events of one profiled call (none when not profiling), taken from the
+// operator's pool under its lock and filed in its record once recorded.
 struct Profiler {
   ftm_operator op;
   hipStream_t st;
-  ftm_operator_s::Rec* rec = nullptr;
-  Profiler(ftm_operator o, hipStream_t s, int dir) : op(o), st(s) {
-    if (!op->profiling) return;
-    ftm_operator_s::Rec r{};
-    r.dir = dir;
-    for (auto& e : r.ev) {
+  bool on;
+  ftm_operator_s::Rec rec{};
+  Profiler(ftm_operator o, hipStream_t s, int dir, bool enabled) : op(o), st(s), on(enabled) {
+    rec.dir = dir;
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(op->mu);
+    for (auto& e : rec.ev) {
       if (!op->event_pool.empty()) {
         e = op->event_pool.back();
         op->event_pool.pop_back();
@@ -210,11 +226,14 @@ struct Profiler {
         e = nullptr;
       }
     }
-    op->recs.push_back(r);
-    rec = &op->recs.back();
   }
   void mark(int i) {
-    if (rec && rec->ev[i]) (void)hipEventRecord(rec->ev[i], st);
+    if (on && rec.ev[i]) (void)hipEventRecord(rec.ev[i], st);
+  }
+  ~Profiler() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(op->mu);
+    op->recs.push_back(rec);
   }
 };
 
@@ -224,9 +243,9 @@ uint32_t needed_mask(const ftm_precision& f, const ftm_precision& a) { return (1
 
 // One direction of the matvec: x (float64, [nrhs][Nt][Sx]) -> y (float64,
 // [nrhs][Nt][Sy]).  adjoint selects Fhat^H in phase 3.
-ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io, int64_t nrhs,
+ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, const MatvecIO& io, int64_t nrhs,
                               const Workspace& ws, hipStream_t st) {
-  const ftm_precision& p = adjoint ? op->adj : op->fwd;
+  const ftm_precision& p = ex.p;
   const void* F = op->spec[p.gemv].p;
   if (!F) return fail(FTM_ERR_STATE, "spectrum for the configured phase-3 precision is missing");
 
@@ -259,7 +278,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io,
   ra.r_fft = p.fft;
   ra.r_next = p.gemv;
   const void* tw_in = p.fft == DT_F64 ? op->tw64.p : op->tw32.p;
-  Profiler prof(op, st, adjoint ? 1 : 0);
+  Profiler prof(op, st, adjoint ? 1 : 0, ex.profile);
   prof.mark(0);
   FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, p.fft == DT_F64 ? op->plan : op->plan32, tw_in, st));
 
@@ -279,14 +298,10 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io,
   ga.y_rhs_stride = ldy;
   ga.r_gemv = p.gemv;
   ga.r_next = p.ifft;
-  ga.variant = op->variant[adjoint ? 1 : 0][p.gemv];
+  ga.variant = ex.gemv_variant;
   const bool acc64 = p.accum == DT_F64;
   prof.mark(1);
-  // many right-hand sides: one pass of the spectrum through the matrix cores
-  const bool gemm_ok = p.gemv != DT_F64 && !acc64 && nrhs >= 2;
-  const bool use_gemm = gemm_ok && (op->rhs_mode == FTM_RHS_GEMM ||
-                                    (op->rhs_mode == FTM_RHS_AUTO && nrhs >= op->gemm_min_rhs));
-  if (use_gemm) {
+  if (ex.use_gemm) {
     if (adjoint) FTM_HIP(launch_gemm_adj(p.gemv, ga, st));
     else FTM_HIP(launch_gemm_fwd(p.gemv, ga, st));
   } else if (adjoint) {
@@ -462,6 +477,7 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
 
 ftm_status ftm_set_precision(ftm_operator op, const ftm_precision* fwd, const ftm_precision* adj) {
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  std::lock_guard<std::mutex> lk(op->mu);
   const ftm_precision pf = fwd ? *fwd : op->fwd, pa = adj ? *adj : op->adj;
   ftm_status s;
   if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
@@ -472,18 +488,30 @@ ftm_status ftm_set_precision(ftm_operator op, const ftm_precision* fwd, const ft
   return FTM_OK;
 }
 
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = reinterpret_cast<const char*>(a);
+  const char* pb = reinterpret_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Validate the arguments of one matvec call (not the workspace).
+static ftm_status check_call(ftm_operator op, bool adjoint, const double* x, double* y, int64_t nrhs,
+                             int64_t max_rhs) {
+  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  if (!x || !y) return fail(FTM_ERR_INVALID, "input or output is NULL");
+  if (nrhs < 1 || nrhs > max_rhs)
+    return fail(FTM_ERR_INVALID, "nrhs must be in [1, " + std::to_string(max_rhs) + "]");
+  const int64_t nx = nrhs * op->Nt * (adjoint ? op->Nd : op->Nm);
+  const int64_t ny = nrhs * op->Nt * (adjoint ? op->Nm : op->Nd);
+  if (overlaps(x, (size_t)nx * 8, y, (size_t)ny * 8)) return fail(FTM_ERR_INVALID, "input and output overlap");
+  return FTM_OK;
+}
+
 static ftm_status matvec_common(ftm_operator op, bool adjoint, const double* x, double* y, int64_t nrhs,
                                 void* stream) {
   try {
-    if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
-    if (!x || !y) return fail(FTM_ERR_INVALID, "input or output is NULL");
-    if (nrhs < 1 || nrhs > op->max_rhs)
-      return fail(FTM_ERR_INVALID, "nrhs must be in [1, max_rhs=" + std::to_string(op->max_rhs) + "]");
-    const int64_t nx = nrhs * op->Nt * (adjoint ? op->Nd : op->Nm);
-    const int64_t ny = nrhs * op->Nt * (adjoint ? op->Nm : op->Nd);
-    const char* xb = reinterpret_cast<const char*>(x);
-    const char* yb = reinterpret_cast<const char*>(y);
-    if (xb < yb + ny * 8 && yb < xb + nx * 8) return fail(FTM_ERR_INVALID, "input and output overlap");
+    ftm_status s = check_call(op, adjoint, x, y, nrhs, op ? op->max_rhs : 0);
+    if (s != FTM_OK) return s;
     DeviceGuard g(op->device);
     ftm_rt::MatvecIO io;
     io.x = x;
@@ -491,9 +519,49 @@ static ftm_status matvec_common(ftm_operator op, bool adjoint, const double* x, 
     ftm_rt::Workspace ws;
     ws.mhat = op->mhat.p;
     ws.dhat = op->dhat.p;
-    return ftm_rt::run_matvec(op, adjoint, io, nrhs, ws, reinterpret_cast<hipStream_t>(stream));
+    return ftm_rt::run_matvec(op, adjoint, op->exec(adjoint, nrhs, true), io, nrhs, ws,
+                              reinterpret_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(FTM_ERR_INVALID, "unexpected exception in matvec");
+  }
+}
+
+// Largest nrhs of a call that brings its own workspace.
+static constexpr int64_t kMaxCallRhs = 1 << 20;
+
+ftm_status ftm_workspace_size(ftm_operator op, int32_t adjoint, int64_t nrhs, size_t* bytes) {
+  if (!op || !bytes) return fail(FTM_ERR_INVALID, "operator or bytes is NULL");
+  if (nrhs < 1 || nrhs > kMaxCallRhs) return fail(FTM_ERR_INVALID, "nrhs must be in [1, 2^20]");
+  const ftm_rt::Exec ex = op->exec(adjoint != 0, nrhs, false);
+  *bytes = op->workspace_bytes(nrhs, adjoint != 0, ex.p);
+  return FTM_OK;
+}
+
+ftm_status ftm_apply(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  try {
+    ftm_status s = check_call(op, adjoint != 0, x, y, nrhs, kMaxCallRhs);
+    if (s != FTM_OK) return s;
+    if (!workspace) return fail(FTM_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(FTM_ERR_INVALID, "workspace must be 256-byte aligned");
+    const bool adj = adjoint != 0;
+    const ftm_rt::Exec ex = op->exec(adj, nrhs, true);
+    const size_t need = op->workspace_bytes(nrhs, adj, ex.p);
+    if (workspace_bytes < need)
+      return fail(FTM_ERR_INVALID, "workspace of " + std::to_string(workspace_bytes) + " bytes, the call needs " +
+                                       std::to_string(need));
+    const int64_t nx = nrhs * op->Nt * (adj ? op->Nd : op->Nm), ny = nrhs * op->Nt * (adj ? op->Nm : op->Nd);
+    if (overlaps(workspace, need, x, (size_t)nx * 8) || overlaps(workspace, need, y, (size_t)ny * 8))
+      return fail(FTM_ERR_INVALID, "workspace overlaps the input or the output");
+    DeviceGuard g(op->device);
+    ftm_rt::MatvecIO io;
+    io.x = x;
+    io.y = y;
+    const ftm_rt::Workspace ws = ftm_rt::carve_workspace(op, workspace, nrhs, adj, ex.p);
+    return ftm_rt::run_matvec(op, adj, ex, io, nrhs, ws, reinterpret_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(FTM_ERR_INVALID, "unexpected exception in ftm_apply");
   }
 }
 
@@ -532,6 +600,7 @@ ftm_status ftm_operator_info(ftm_operator op, int64_t* Nt, int64_t* Nd, int64_t*
 ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode) {
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
   if (mode < FTM_RHS_AUTO || mode > FTM_RHS_GEMM) return fail(FTM_ERR_INVALID, "unknown rhs mode");
+  std::lock_guard<std::mutex> lk(op->mu);
   op->rhs_mode = mode;
   return FTM_OK;
 }
@@ -539,12 +608,14 @@ ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode) {
 ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs) {
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
   if (min_rhs < 2) return fail(FTM_ERR_INVALID, "the crossover is at least 2 right-hand sides");
+  std::lock_guard<std::mutex> lk(op->mu);
   op->gemm_min_rhs = min_rhs;
   return FTM_OK;
 }
 
 ftm_status ftm_profile_enable(ftm_operator op, int32_t enable) {
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  std::lock_guard<std::mutex> lk(op->mu);
   op->profiling = enable != 0;
   return FTM_OK;
 }
@@ -554,6 +625,7 @@ ftm_status ftm_profile_read(ftm_operator op, double* ms, int64_t* counts, int32_
   double acc[6] = {0, 0, 0, 0, 0, 0};
   int64_t cnt[2] = {0, 0};
   DeviceGuard g(op->device);
+  std::lock_guard<std::mutex> lk(op->mu);
   for (const auto& r : op->recs) {
     bool ok = true;
     for (hipEvent_t e : r.ev) ok = ok && e != nullptr;
@@ -607,48 +679,47 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
   if (hipMemsetAsync(x.p, 0x3f, x.n, st) != hipSuccess) return done(fail(FTM_ERR_HIP, "hipMemsetAsync"));
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return done(fail(FTM_ERR_HIP, "hipEventCreate"));
-  const bool prof = op->profiling;
-  op->profiling = false;
   ftm_rt::Workspace ws;
   ws.mhat = op->mhat.p;
   ws.dhat = op->dhat.p;
+  int best_v[2] = {0, 0};
+  double best_t[2] = {1e300, 1e300};
+  ftm_rt::Exec ex[2];
   for (int dir = 0; dir < 2; ++dir) {
-    const int dt = (dir ? op->adj : op->fwd).gemv;
+    ex[dir] = op->exec(dir == 1, 1, false);
     ftm_rt::MatvecIO io;
     io.x = reinterpret_cast<const double*>(x.p);
     io.y = reinterpret_cast<double*>(y.p);
-    int best = 0;
-    double best_ms = 1e300;
     for (int v = 0; v < GEMV_VARIANTS; ++v) {
-      op->variant[dir][dt] = v;
-      if ((s = ftm_rt::run_matvec(op, dir == 1, io, 1, ws, st)) != FTM_OK) {
-        op->profiling = prof;
-        return done(s);
-      }
+      ex[dir].gemv_variant = v;
+      if ((s = ftm_rt::run_matvec(op, dir == 1, ex[dir], io, 1, ws, st)) != FTM_OK) return done(s);
       (void)hipEventRecord(e0, st);
-      for (int r = 0; r < reps; ++r) ftm_rt::run_matvec(op, dir == 1, io, 1, ws, st);
+      for (int r = 0; r < reps; ++r) ftm_rt::run_matvec(op, dir == 1, ex[dir], io, 1, ws, st);
       (void)hipEventRecord(e1, st);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        op->profiling = prof;
-        return done(fail(FTM_ERR_HIP, "hipEventSynchronize"));
-      }
+      if (hipEventSynchronize(e1) != hipSuccess) return done(fail(FTM_ERR_HIP, "hipEventSynchronize"));
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms / reps < best_ms) {
-        best_ms = ms / reps;
-        best = v;
+      if (ms / reps < best_t[dir]) {
+        best_t[dir] = ms / reps;
+        best_v[dir] = v;
       }
     }
-    op->variant[dir][dt] = best;
-    op->tuned_ms[dir] = best_ms;
   }
-  op->profiling = prof;
+  {
+    // keep the winners for the storage formats they were timed with
+    std::lock_guard<std::mutex> lk(op->mu);
+    for (int dir = 0; dir < 2; ++dir) {
+      op->variant[dir][ex[dir].p.gemv] = best_v[dir];
+      op->tuned_ms[dir] = best_t[dir];
+    }
+  }
   return done(FTM_OK);
 }
 
 ftm_status ftm_get_tuning(ftm_operator op, int32_t* fwd_variant, int32_t* adj_variant, double* fwd_ms,
                           double* adj_ms) {
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+  std::lock_guard<std::mutex> lk(op->mu);
   if (fwd_variant) *fwd_variant = op->variant[0][op->fwd.gemv];
   if (adj_variant) *adj_variant = op->variant[1][op->adj.gemv];
   if (fwd_ms) *fwd_ms = op->tuned_ms[0];
@@ -660,6 +731,7 @@ ftm_status ftm_set_tuning(ftm_operator op, int32_t fwd_variant, int32_t adj_vari
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
   if (fwd_variant < 0 || fwd_variant >= GEMV_VARIANTS || adj_variant < 0 || adj_variant >= GEMV_VARIANTS)
     return fail(FTM_ERR_INVALID, "variant out of range");
+  std::lock_guard<std::mutex> lk(op->mu);
   op->variant[0][op->fwd.gemv] = fwd_variant;
   op->variant[1][op->adj.gemv] = adj_variant;
   return FTM_OK;
@@ -682,8 +754,6 @@ ftm_status ftm_graph_create(ftm_graph* out, ftm_operator op, int32_t adjoint, co
   FTM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   ftm_graph gr = new ftm_graph_s();
   gr->device = op->device;
-  const bool prof = op->profiling;
-  op->profiling = false;  // no event records inside the graph
   ftm_rt::MatvecIO io;
   io.x = x;
   io.y = y;
@@ -693,11 +763,11 @@ ftm_status ftm_graph_create(ftm_graph* out, ftm_operator op, int32_t adjoint, co
   ftm_status s = FTM_OK;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    s = ftm_rt::run_matvec(op, adjoint != 0, io, nrhs, ws, cs);
+    // no event records inside the graph
+    s = ftm_rt::run_matvec(op, adjoint != 0, op->exec(adjoint != 0, nrhs, false), io, nrhs, ws, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &gr->graph);
     if (s == FTM_OK && e2 != hipSuccess) e = e2;
   }
-  op->profiling = prof;
   if (e == hipSuccess && s == FTM_OK) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cs);
   if (e != hipSuccess || s != FTM_OK) {

@@ -1,10 +1,11 @@
 // Host runtime internals shared by the C ABI (ftm_api.hip) and the serving
 // scheduler (ftm_server.hip): the operator object, error reporting and the
-// stream-ordered three-kernel chain of one matvec.
+// stream-ordered kernel chain of one matvec.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,8 +20,8 @@ struct DevBuf {
 };
 
 // Device workspace of one matvec: the transformed input and output vectors,
-// [K][nrhs][ld] complex each, float64-sized (float32 intermediates use the
-// first half).
+// [K][nrhs][ld] complex each, in the intermediate storage formats of the
+// direction's precision configuration.
 struct Workspace {
   void* mhat = nullptr;
   void* dhat = nullptr;
@@ -36,6 +37,17 @@ struct MatvecIO {
   double* const* yptr = nullptr;
 };
 
+// Everything a matvec reads from the operator's mutable configuration, copied
+// under the operator's lock when the call is made: a concurrent
+// ftm_set_precision / ftm_set_tuning cannot change a call that is being
+// enqueued, and its workspace is sized for the configuration it runs.
+struct Exec {
+  ftm_precision p{};
+  int gemv_variant = 0;
+  bool use_gemm = false;
+  bool profile = false;  // record HIP events around the kernels
+};
+
 }  // namespace ftm_rt
 
 struct ftm_operator_s {
@@ -47,13 +59,14 @@ struct ftm_operator_s {
   ftm_rt::DevBuf tw64, tw32;     // their per-pass twiddle tables
   ftm_rt::DevBuf spec[4];     // Fhat[K][Nd][ldm] per storage format
   ftm_rt::DevBuf mhat, dhat;  // the operator's own workspace, sized for max_rhs
+
+  // Mutable configuration and instrumentation; every access holds mu.
+  mutable std::mutex mu;
   ftm_precision fwd{}, adj{};
   int rhs_mode = FTM_RHS_AUTO;
   int64_t gemm_min_rhs = 2;
   int variant[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // [direction][storage format] tile variant
   double tuned_ms[2] = {0.0, 0.0};
-
-  // instrumentation: events around the three kernels of each recorded call
   bool profiling = false;
   struct Rec {
     int dir;
@@ -67,28 +80,25 @@ struct ftm_operator_s {
     for (const auto& s : spec) b += s.n;
     return b;
   }
-  // workspace bytes a matvec of nrhs right-hand sides needs in any precision
-  // configuration (float64 intermediates)
-  size_t workspace_bytes(int64_t nrhs) const {
-    return (size_t)K * nrhs * (ldm + ldd) * 16 + 512;
-  }
-  // bytes per complex entry of m-hat and d-hat in one direction at the
-  // current configuration: float64 (16) where both neighbouring phases are
-  // float64, else float32 (8)
-  void workspace_elems(bool adjoint, int* em, int* ed) const {
-    const ftm_precision& p = adjoint ? adj : fwd;
+  static size_t round256(size_t n) { return (n + 255) / 256 * 256; }
+  // bytes per complex entry of m-hat and d-hat in one direction of
+  // configuration p: float64 (16) where both neighbouring phases are float64,
+  // else float32 (8)
+  static void workspace_elems(const ftm_precision& p, bool adjoint, int* em, int* ed) {
     const int ex = (p.fft == 0 && p.gemv == 0) ? 16 : 8;   // transformed input
     const int ey = (p.gemv == 0 && p.ifft == 0) ? 16 : 8;  // transformed output
     *em = adjoint ? ey : ex;
     *ed = adjoint ? ex : ey;
   }
-  static size_t round256(size_t n) { return (n + 255) / 256 * 256; }
-  // workspace bytes of one matvec in one direction at the current configuration
-  size_t workspace_bytes(int64_t nrhs, bool adjoint) const {
+  // workspace bytes of one matvec of nrhs right-hand sides in one direction at
+  // configuration p (a multiple of 256: m-hat, then d-hat at a 256-byte offset)
+  size_t workspace_bytes(int64_t nrhs, bool adjoint, const ftm_precision& p) const {
     int em, ed;
-    workspace_elems(adjoint, &em, &ed);
-    return round256((size_t)K * nrhs * ldm * em) + (size_t)K * nrhs * ldd * ed + 512;
+    workspace_elems(p, adjoint, &em, &ed);
+    return round256((size_t)K * nrhs * ldm * em) + round256((size_t)K * nrhs * ldd * ed);
   }
+  // the copy of the direction's configuration a call runs with (locks mu)
+  ftm_rt::Exec exec(bool adjoint, int64_t nrhs, bool allow_profile) const;
 };
 
 namespace ftm_rt {
@@ -118,13 +128,12 @@ class DeviceGuard {
   bool switched_ = false;
 };
 
-// Split a workspace block of op->workspace_bytes(nrhs, adjoint) bytes for a
-// matvec in that direction at the operator's current configuration.
-Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs, bool adjoint);
+// Split a workspace block of op->workspace_bytes(nrhs, adjoint, p) bytes.
+Workspace carve_workspace(const ftm_operator_s* op, void* base, int64_t nrhs, bool adjoint, const ftm_precision& p);
 
-// Enqueue one matvec (phases 1-5) on st.  No argument checks: callers
-// validate.
-ftm_status run_matvec(ftm_operator op, bool adjoint, const MatvecIO& io, int64_t nrhs, const Workspace& ws,
-                      hipStream_t st);
+// Enqueue one matvec (phases 1-5) on st with the configuration ex.  No
+// argument checks: callers validate.
+ftm_status run_matvec(ftm_operator op, bool adjoint, const Exec& ex, const MatvecIO& io, int64_t nrhs,
+                      const Workspace& ws, hipStream_t st);
 
 }  // namespace ftm_rt

@@ -26,8 +26,10 @@
 #include <vector>
 
 #include "ftm.h"
+#include "ftm_arena.h"
 #include "ftm_runtime.h"
 
+using ftm_rt::Arena;
 using ftm_rt::fail;
 using ftm_rt::fail_hip;
 
@@ -37,53 +39,6 @@ double now_s() {
   using clk = std::chrono::steady_clock;
   return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
 }
-
-// First-fit sub-allocator over one device block (offsets, 256-byte granules).
-class Arena {
- public:
-  void reset(size_t size) {
-    free_.clear();
-    free_[0] = size;
-    used_ = 0;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = round(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes, start = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[start] = rest;
-        used_ += bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = round(bytes);
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t used() const { return used_; }
-
- private:
-  static size_t round(size_t b) { return (b + 255) / 256 * 256; }
-  std::map<size_t, size_t> free_;
-  size_t used_ = 0;
-};
 
 struct Request {
   uint64_t ticket;
@@ -111,6 +66,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   bool busy = false;
   std::vector<Request> reqs;
+  ftm_rt::Exec ex;  // the batch's configuration, copied when it was admitted
   size_t ws_off = 0, ws_bytes = 0;
   int64_t nrhs = 0;
   const double** h_ptrs = nullptr;  // pinned: [max_rhs] inputs then [max_rhs] outputs
@@ -142,7 +98,9 @@ struct ftm_server_s {
   int64_t inflight_requests = 0;
 
   void run();
-  void launch(Slot& s, std::vector<Request>&& batch, size_t off, size_t bytes, int64_t nrhs);
+  void launch(Slot& s, std::vector<Request>&& batch, const ftm_rt::Exec& ex, size_t off, size_t bytes,
+              int64_t nrhs);
+  void fail_head(const std::string& why);
 };
 
 static void on_batch_done(void* user) {
@@ -163,9 +121,11 @@ static void on_batch_done(void* user) {
   srv->cv_done.notify_all();
 }
 
-void ftm_server_s::launch(Slot& s, std::vector<Request>&& batch, size_t off, size_t bytes, int64_t nrhs) {
+void ftm_server_s::launch(Slot& s, std::vector<Request>&& batch, const ftm_rt::Exec& ex, size_t off, size_t bytes,
+                          int64_t nrhs) {
   s.busy = true;
   s.reqs = std::move(batch);
+  s.ex = ex;
   s.ws_off = off;
   s.ws_bytes = bytes;
   s.nrhs = nrhs;
@@ -198,8 +158,9 @@ void ftm_server_s::launch(Slot& s, std::vector<Request>&& batch, size_t off, siz
     ftm_rt::MatvecIO io;
     io.xptr = reinterpret_cast<const double* const*>(s.d_ptrs);
     io.yptr = reinterpret_cast<double* const*>(s.d_ptrs) + max_batch_rhs;
-    const ftm_rt::Workspace ws = ftm_rt::carve_workspace(op, reinterpret_cast<char*>(arena_base) + off, nrhs, adj);
-    st = ftm_rt::run_matvec(op, adj, io, nrhs, ws, s.stream);
+    const ftm_rt::Workspace ws =
+        ftm_rt::carve_workspace(op, reinterpret_cast<char*>(arena_base) + off, nrhs, adj, s.ex.p);
+    st = ftm_rt::run_matvec(op, adj, s.ex, io, nrhs, ws, s.stream);
     if (st == FTM_OK) e = hipLaunchHostFunc(s.stream, on_batch_done, &s.ctx);
   }
   mu.lock();
@@ -215,6 +176,17 @@ void ftm_server_s::launch(Slot& s, std::vector<Request>&& batch, size_t off, siz
     s.busy = false;
     cv_done.notify_all();
   }
+}
+
+// Fail the queue head (the lock is held).
+void ftm_server_s::fail_head(const std::string& why) {
+  const Request& head = queue.front();
+  error = why;
+  state[head.ticket - 1] = ST_FAILED;
+  stats.failed += 1;
+  inflight_requests -= 1;
+  queue.pop_front();
+  cv_done.notify_all();
 }
 
 void ftm_server_s::run() {
@@ -235,22 +207,19 @@ void ftm_server_s::run() {
     // admit: oldest request first, coalescing same-operator same-direction requests
     while (!queue.empty()) {
       Slot* free_slot = nullptr;
-      for (auto& s : slots)
-        if (!s.busy) {
-          free_slot = &s;
-          break;
-        }
+      bool any_busy = false;
+      for (auto& s : slots) {
+        if (!s.busy && !free_slot) free_slot = &s;
+        any_busy = any_busy || s.busy;
+      }
       if (!free_slot) break;
       const Request head = queue.front();
-      if (head.op->workspace_bytes(head.nrhs, head.adjoint) > budget) {
+      // the batch runs the configuration its operator has now
+      const ftm_rt::Exec ex0 = head.op->exec(head.adjoint, head.nrhs, false);
+      if (Arena::need(head.op->workspace_bytes(head.nrhs, head.adjoint, ex0.p)) > arena.capacity()) {
         // the operator's precision changed after submit to one whose
         // workspace exceeds the whole budget: this request can never run
-        error = "request needs more workspace than the whole budget at the operator's current precision";
-        state[head.ticket - 1] = ST_FAILED;
-        stats.failed += 1;
-        inflight_requests -= 1;
-        queue.erase(queue.begin());
-        cv_done.notify_all();
+        fail_head("request needs more workspace than the whole budget at the operator's current precision");
         continue;
       }
       std::vector<size_t> take{0};
@@ -262,7 +231,8 @@ void ftm_server_s::run() {
           total += r.nrhs;
         }
       }
-      size_t off = 0, bytes = head.op->workspace_bytes(total, head.adjoint);
+      ftm_rt::Exec ex = head.op->exec(head.adjoint, total, false);
+      size_t off = 0, bytes = head.op->workspace_bytes(total, head.adjoint, ex.p);
       while (!arena.alloc(bytes, &off)) {
         // shrink the batch from the back until it fits; the head alone may
         // have to wait for running batches to release workspace
@@ -272,9 +242,16 @@ void ftm_server_s::run() {
         }
         total -= queue[take.back()].nrhs;
         take.pop_back();
-        bytes = head.op->workspace_bytes(total, head.adjoint);
+        ex = head.op->exec(head.adjoint, total, false);
+        bytes = head.op->workspace_bytes(total, head.adjoint, ex.p);
       }
       if (bytes == 0) {
+        if (!any_busy) {
+          // cannot happen (the head fits an empty arena), but never wait for a
+          // release that no running batch will make
+          fail_head("request does not fit the empty workspace arena");
+          continue;
+        }
         stats.budget_waits += 1;
         budget_blocked = true;
         break;
@@ -283,21 +260,23 @@ void ftm_server_s::run() {
       batch.reserve(take.size());
       for (size_t t : take) batch.push_back(queue[t]);
       for (size_t t = take.size(); t-- > 0;) queue.erase(queue.begin() + (std::ptrdiff_t)take[t]);
-      launch(*free_slot, std::move(batch), off, bytes, total);
+      launch(*free_slot, std::move(batch), ex, off, bytes, total);
     }
 
     bool busy = false;
     for (auto& s : slots) busy = busy || s.busy;
     if (stop && queue.empty() && !busy) break;
-    // sleep until a batch completes, or until there is queued work, a free
-    // slot and no head blocked on the budget
+    // sleep until a batch completes, until there is queued work, a free slot
+    // and no head blocked on the budget, or until a stop can finish
     cv_work.wait(lk, [&] {
       if (!completed.empty()) return true;
-      if (stop) return true;
-      if (queue.empty() || budget_blocked) return false;
-      for (auto& s : slots)
-        if (!s.busy) return true;
-      return false;
+      bool any_busy = false, any_free = false;
+      for (auto& s : slots) {
+        any_busy = any_busy || s.busy;
+        any_free = any_free || !s.busy;
+      }
+      if (stop && queue.empty() && !any_busy) return true;
+      return !queue.empty() && !budget_blocked && any_free;
     });
   }
 }
@@ -355,10 +334,11 @@ ftm_status ftm_server_submit(ftm_server s, ftm_operator op, int32_t adjoint, con
   if (nrhs < 1 || nrhs > s->max_batch_rhs)
     return fail(FTM_ERR_INVALID, "nrhs must be in [1, max_batch_rhs=" + std::to_string(s->max_batch_rhs) + "]");
   if (op->device != s->device) return fail(FTM_ERR_INVALID, "operator lives on another device");
-  const ftm_precision& p = adjoint ? op->adj : op->fwd;
-  if (!op->spec[p.gemv].p) return fail(FTM_ERR_STATE, "spectrum for the configured precision is missing");
-  if (op->workspace_bytes(nrhs, adjoint != 0) > s->budget)
-    return fail(FTM_ERR_BUDGET, "request needs " + std::to_string(op->workspace_bytes(nrhs, adjoint != 0)) +
+  const ftm_rt::Exec ex = op->exec(adjoint != 0, nrhs, false);
+  if (!op->spec[ex.p.gemv].p) return fail(FTM_ERR_STATE, "spectrum for the configured precision is missing");
+  const size_t need = Arena::need(op->workspace_bytes(nrhs, adjoint != 0, ex.p));
+  if (need > s->arena.capacity())
+    return fail(FTM_ERR_BUDGET, "request needs " + std::to_string(need) +
                                     " workspace bytes, more than the whole budget");
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -184,6 +184,44 @@ def test_multi_rhs_matches_single_bitwise(gpu):
     assert _rel(batch_m, oracle.adjoint(F, D)) <= FP64_TOL
 
 
+def test_apply_on_caller_workspaces_concurrently(gpu):
+    """ftm_apply on two NaN-filled caller workspaces, on two streams at once:
+    both results equal the operator's own-workspace call bitwise."""
+    import torch
+    from paper_2508_10202_amd import FtmError, Operator
+    s = Shape(64, 20, 500)
+    F, M, D = make_F(s, 57), make_m(s, 58, nrhs=3), make_d(s, 59, nrhs=3)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s",), max_rhs=3)
+    Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
+    for prec in ("ddddd", "dssdd"):
+        op.set_precision(fwd=prec, adj=prec)
+        want_d, want_m = op.matvec(Mt).clone(), op.rmatvec(Dt).clone()
+        nb = max(op.workspace_size(5, adjoint=a) for a in (False, True))
+        ws = [torch.full((nb // 8 + 1,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(2)]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        torch.cuda.synchronize()
+        outs = []
+        for rep in range(3):
+            with torch.cuda.stream(streams[0]):
+                yd = op.apply(Mt, ws[0], stream=streams[0])
+            with torch.cuda.stream(streams[1]):
+                ym = op.apply(Dt, ws[1], adjoint=True, stream=streams[1])
+            outs.append((yd, ym))
+        torch.cuda.synchronize()
+        for yd, ym in outs:
+            assert torch.equal(yd, want_d) and torch.equal(ym, want_m), prec
+    # a workspace one byte short, or misaligned, is refused
+    ws = torch.empty(op.workspace_size(3) + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(FtmError) as ei:
+        op.apply(Mt, ws[: op.workspace_size(3) - 1])
+    assert ei.value.status == 1
+    with pytest.raises(FtmError) as ei:
+        op.apply(Mt, ws[8:])
+    assert ei.value.status == 1
+    op.close()
+    assert _rel(want_d.cpu().numpy(), oracle.forward(F, M)) <= 1e-6
+
+
 def test_repeat_is_bitwise_deterministic(gpu):
     import torch
     from paper_2508_10202_amd import Operator

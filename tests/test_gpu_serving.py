@@ -100,7 +100,7 @@ def test_tiny_budget_queues_instead_of_failing(gpu, ops):
     from paper_2508_10202_amd import Server
     for _, _, op in ops:
         op.set_precision(fwd="ddddd", adj="ddddd")
-    need = max(_ws(op, 8) for _, _, op in ops)
+    need = max(op.workspace_size(8, adjoint=a) for _, _, op in ops for a in (False, True))
     reqs = _requests(ops, 40, seed=3)
     xs = [torch.from_numpy(x).cuda() for _, _, x in reqs]
     torch.cuda.synchronize()
@@ -120,19 +120,13 @@ def test_tiny_budget_queues_instead_of_failing(gpu, ops):
 
 
 def _ws(op, nrhs):
-    """Workspace bytes of one batch, as the library sizes it."""
-    K = op.K
-    ldm, ldd = (op.Nm + 7) // 8 * 8, (op.Nd + 7) // 8 * 8
-    return K * nrhs * (ldm + ldd) * 16 + 512 + 512
-
-
-def _ws32(op, nrhs):
-    """Workspace bytes of one batch whose transformed vectors are float32 (the
-    library's sizing, rounded to the arena's 256-byte grain)."""
-    K = op.K
-    ldm, ldd = (op.Nm + 7) // 8 * 8, (op.Nd + 7) // 8 * 8
-    m = (K * nrhs * ldm * 8 + 255) // 256 * 256
-    return (m + K * nrhs * ldd * 8 + 512 + 255) // 256 * 256
+    """Workspace bytes of one float64 batch (both directions' maximum), as the
+    library sizes it."""
+    keep = (op.fwd, op.adj)
+    op.set_precision(fwd="ddddd", adj="ddddd")
+    n = max(op.workspace_size(nrhs, adjoint=a) for a in (False, True))
+    op.set_precision(fwd=keep[0], adj=keep[1])
+    return n
 
 
 def test_float32_batches_take_float32_workspace(gpu, ops):
@@ -142,8 +136,11 @@ def test_float32_batches_take_float32_workspace(gpu, ops):
     import torch
     from paper_2508_10202_amd import FtmError, Server
     s, F, op = ops[1]
-    budget = _ws32(op, 8)
-    assert budget < _ws(op, 8)
+    op.set_precision(fwd="sssss", adj="sssss")
+    budget = op.workspace_size(8)
+    op.set_precision(fwd="ddddd", adj="ddddd")
+    assert budget < op.workspace_size(8)
+    budget += 255                       # not a multiple of the arena's 256-byte granule
     x = normal((8, s.Nt, s.Nm), 4242)
     xt = torch.from_numpy(x).cuda()
     try:
@@ -179,3 +176,55 @@ def test_request_beyond_budget_is_rejected(gpu, ops):
         assert ei.value.status == 4            # FTM_ERR_BUDGET
         t, y = srv.submit(op, x[:1])           # one vector fits
         srv.wait(t, timeout=60)
+
+
+def test_budget_not_a_multiple_of_the_granule(gpu, ops):
+    """The budget is used in 256-byte granules: a budget a little above one
+    request's workspace admits it, one byte below rejects it at submit."""
+    import torch
+    from paper_2508_10202_amd import FtmError, Server
+    s, F, op = ops[0]
+    op.set_precision(fwd="sssss", adj="sssss")
+    try:
+        need = op.workspace_size(1)
+        assert need % 256 == 0
+        x = torch.from_numpy(normal((1, s.Nt, s.Nm), 777)).cuda()
+        with Server(workspace_budget=need + 100, n_slots=1, max_batch_rhs=1) as srv:
+            t, y = srv.submit(op, x)
+            srv.wait(t, timeout=60)
+            assert oracle.relative_l2(y.cpu().numpy(), oracle.forward(F, x.cpu().numpy())) <= 2e-5
+        with Server(workspace_budget=need - 1, n_slots=1, max_batch_rhs=1) as srv:
+            with pytest.raises(FtmError) as ei:
+                srv.submit(op, x)
+            assert ei.value.status == 4
+    finally:
+        op.set_precision(fwd="ddddd", adj="ddddd")
+
+
+def test_precision_change_while_queued(gpu, ops):
+    """Switching an operator between float32 and float64 intermediates while
+    its requests queue: each batch is sized and run with the configuration it
+    was admitted with, so every request completes and is correct."""
+    import torch
+    from paper_2508_10202_amd import Server
+    s, F, op = ops[1]
+    x = normal((4, s.Nt, s.Nm), 888)
+    xt = torch.from_numpy(x).cuda()
+    ref = oracle.forward(F, x)
+    budget = 3 * op.workspace_size(8)            # float64 sizing (the larger)
+    tickets = []
+    try:
+        with Server(workspace_budget=budget, n_slots=2, max_batch_rhs=8) as srv:
+            for i in range(40):
+                op.set_precision(fwd="sssss" if i % 2 else "ddddd")
+                tickets.append(srv.submit(op, xt))
+            for t, _ in tickets:
+                srv.wait(t, timeout=60)
+            st = srv.stats()
+    finally:
+        op.set_precision(fwd="ddddd", adj="ddddd")
+    _say(f"  precision switching: {st}")
+    assert st["completed"] == 40 and st["failed"] == 0
+    assert st["peak_workspace_bytes"] <= budget
+    for t, y in tickets:
+        assert oracle.relative_l2(y.cpu().numpy(), ref) <= 2e-5
