@@ -141,6 +141,26 @@ ftm_status ftm_workspace_size(ftm_operator op, int32_t adjoint, int64_t nrhs, si
 ftm_status ftm_apply(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* Bytes of the library's static scratch workspace on each GPU (96 MiB: one
+ * float64 vector at Nt=1000, Nd=100, Nm=5000 needs 81.8 MB). */
+#define FTM_SCRATCH_BYTES ((size_t)96 << 20)
+
+/* ftm_apply without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the transformed vectors live in a static
+ * FTM_SCRATCH_BYTES array of the library, one per GPU, which each GPU holds
+ * from the first call on it until the process ends.  The call allocates
+ * nothing (no hipMalloc, no events) and records no profiling events.
+ *   x, y   as for ftm_apply.
+ * All calls on one GPU share its scratch, and it keeps the last call's
+ * contents (no call depends on them): calls that overlap on one GPU (on
+ * different streams, or from different threads without ordering) race and
+ * must not be issued.
+ * FTM_ERR_UNSUPPORTED: the call needs more than FTM_SCRATCH_BYTES of
+ * workspace (ftm_workspace_size); FTM_ERR_INVALID: as for ftm_apply. */
+ftm_status ftm_apply_scratch(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs,
+                             void* stream);
+
 /* How phase 3 treats nrhs > 1 right-hand sides:
  *   FTM_RHS_AUTO  (default) matrix-core GEMM when the product's storage is
  *                 FP32/FP16/BF16 with FP32 accumulation and nrhs >= the

@@ -22,10 +22,12 @@ RHS_AUTO, RHS_GEMV, RHS_GEMM = range(3)
 # ftm_gemv_type, ftm_gemv_op
 TYPE_S, TYPE_D, TYPE_C, TYPE_Z = range(4)
 OP_N, OP_T, OP_C = range(3)
+# FTM_SCRATCH_BYTES: size of the static scratch workspace of ftm_apply_scratch
+SCRATCH_BYTES = 96 << 20
 
 # Every symbol include/ftm.h declares.
 EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
-           "ftm_workspace_size", "ftm_apply",
+           "ftm_workspace_size", "ftm_apply", "ftm_apply_scratch",
            "ftm_get_spectrum", "ftm_operator_info", "ftm_profile_enable", "ftm_profile_read",
            "ftm_set_rhs_mode", "ftm_set_gemm_crossover", "ftm_autotune", "ftm_get_tuning",
            "ftm_set_tuning", "ftm_graph_create", "ftm_graph_launch", "ftm_graph_destroy",
@@ -75,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "ftm_rmatvec": [vp, vp, vp, i64, vp],
         "ftm_workspace_size": [vp, i32, i64, ctypes.POINTER(ctypes.c_size_t)],
         "ftm_apply": [vp, i32, vp, vp, i64, vp, ctypes.c_size_t, vp],
+        "ftm_apply_scratch": [vp, i32, vp, vp, i64, vp],
         "ftm_get_spectrum": [vp, i32, i64, i64, vp, vp],
         "ftm_operator_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                               ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],

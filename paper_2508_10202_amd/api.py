@@ -196,6 +196,29 @@ class Operator:
                                   workspace.data_ptr(), nbytes, _stream_ptr(stream)), "ftm_apply")
         return out[0] if single and out.dim() == 3 else out
 
+    def apply_scratch(self, x: torch.Tensor, adjoint: bool = False, out=None, stream=None) -> torch.Tensor:
+        """``F x`` (or ``F^T x``) on the library's static per-GPU scratch
+        (``ftm_apply_scratch``): the call allocates no device memory.  ``out``
+        must be given by callers that cannot allocate.  Calls that overlap on
+        one GPU race on the shared scratch."""
+        n_in, n_out = (self.Nd, self.Nm) if adjoint else (self.Nm, self.Nd)
+        x = _dev_f64(x, "x")
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        if xb.dim() != 3 or tuple(xb.shape[1:]) != (self.Nt, n_in):
+            raise ValueError(f"input must be [nrhs,] {self.Nt} x {n_in}, got {tuple(x.shape)}")
+        nrhs = xb.shape[0]
+        if out is None:
+            out = torch.empty((nrhs, self.Nt, n_out), dtype=torch.float64, device=x.device)
+        else:
+            out = _dev_f64(out, "out")
+            if out.numel() != nrhs * self.Nt * n_out:
+                raise ValueError("out has the wrong size")
+        with torch.cuda.device(x.device):
+            check(lib().ftm_apply_scratch(self.handle, 1 if adjoint else 0, xb.data_ptr(), out.data_ptr(), nrhs,
+                                          _stream_ptr(stream)), "ftm_apply_scratch")
+        return out[0] if single and out.dim() == 3 else out
+
     def spectrum(self, which="d", k0: int = 0, nk: int | None = None, stream=None) -> torch.Tensor:
         """Stored ``Fhat_k`` for ``k0 <= k < k0 + nk`` as complex128 ``[nk, Nd, Nm]``."""
         nk = (self.K - k0) if nk is None else nk

@@ -565,6 +565,57 @@ ftm_status ftm_apply(ftm_operator op, int32_t adjoint, const double* x, double* 
   }
 }
 
+// ---- the library's static scratch workspace ------------------------------------
+// FTM_SCRATCH_BYTES of device memory per GPU, held from the first
+// ftm_apply_scratch call on that GPU until the process ends.  In host code the
+// array's name is only a stand-in: kernels receive the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[FTM_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array (device dev current).
+ftm_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(FTM_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail_hip("hipGetSymbolAddress(scratch)", e != hipSuccess ? e : hipErrorUnknown);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FTM_OK;
+}
+}  // namespace
+
+ftm_status ftm_apply_scratch(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs,
+                             void* stream) {
+  try {
+    ftm_status s = check_call(op, adjoint != 0, x, y, nrhs, kMaxCallRhs);
+    if (s != FTM_OK) return s;
+    const bool adj = adjoint != 0;
+    const ftm_rt::Exec ex = op->exec(adj, nrhs, false);  // no profiling events: nothing is created
+    const size_t need = op->workspace_bytes(nrhs, adj, ex.p);
+    if (need > (size_t)FTM_SCRATCH_BYTES)
+      return fail(FTM_ERR_UNSUPPORTED, "the call needs " + std::to_string(need) + " bytes of workspace, the static "
+                                       "scratch holds " + std::to_string((size_t)FTM_SCRATCH_BYTES));
+    DeviceGuard g(op->device);
+    void* base = nullptr;
+    if ((s = scratch_address(op->device, &base)) != FTM_OK) return s;
+    ftm_rt::MatvecIO io;
+    io.x = x;
+    io.y = y;
+    const ftm_rt::Workspace ws = ftm_rt::carve_workspace(op, base, nrhs, adj, ex.p);
+    return ftm_rt::run_matvec(op, adj, ex, io, nrhs, ws, reinterpret_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(FTM_ERR_INVALID, "unexpected exception in ftm_apply_scratch");
+  }
+}
+
 ftm_status ftm_matvec(ftm_operator op, const double* m, double* d, int64_t nrhs, void* stream) {
   return matvec_common(op, false, m, d, nrhs, stream);
 }

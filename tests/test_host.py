@@ -148,3 +148,5 @@ def test_binding_constants_match_the_header():
         (_lib.F64, _lib.F32, _lib.F16, _lib.BF16)
     assert (enum("FTM_RHS_AUTO"), enum("FTM_RHS_GEMV"), enum("FTM_RHS_GEMM")) == \
         (_lib.RHS_AUTO, _lib.RHS_GEMV, _lib.RHS_GEMM)
+    m = re.search(r"#define FTM_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.SCRATCH_BYTES
