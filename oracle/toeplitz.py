@@ -16,8 +16,10 @@ Pins (checked by ``tests/test_oracle_pins.py`` against things other than this
 module): the dense block matrix assembled as printed in eq. (ShiftInvariance),
 the adjoint identity, identity/delay blocks, the scalar case as a truncated
 causal convolution (``numpy.convolve``), the geometric kernel's recursion,
-``Nt = 1`` as a plain matrix-vector product, time-shift invariance, and the
-spectrum against closed forms and ``numpy.fft.rfft``.
+``Nt = 1`` as a plain matrix-vector product, time-shift invariance, the
+spectrum against closed forms and ``numpy.fft.rfft``, and the data-space
+Hessian against the dense ``A A^T``, its symmetry and positive
+semidefiniteness.
 """
 from __future__ import annotations
 
@@ -67,6 +69,17 @@ def adjoint(F: np.ndarray, d: np.ndarray) -> np.ndarray:
     for t in range(Nt):
         m[..., : Nt - t, :] += d[..., t:, :] @ F[t]
     return m
+
+
+def hessian_data_space(F: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Data-space Hessian action ``F Gamma F^T x`` with ``Gamma = I``.
+
+    The outer-loop problems of Section 3.2 assemble the dense data-space
+    Hessian ``F Gamma F^*`` column by column (``Nd Nt`` actions); with the
+    identity prior each action is the adjoint product followed by the forward
+    one, by definition.  ``x`` is ``[..., Nt, Nd]``; so is the result.
+    """
+    return forward(F, adjoint(F, x))
 
 
 # --- single entries, computed exactly and rounded once ----------------------

@@ -326,3 +326,35 @@ def test_inputs_are_not_float32_representable():
 def test_relative_l2():
     ref = np.array([3.0, 4.0])
     assert oracle.relative_l2(ref + np.array([0.0, 0.5]), ref) == pytest.approx(0.1)
+
+
+# --- the data-space Hessian F Gamma F^T (Gamma = I) ---------------------------------
+
+def test_hessian_matches_dense_product():
+    """Against the dense A A^T of the block matrix of eq. (ShiftInvariance)."""
+    for Nt, Nd, Nm in ((5, 3, 4), (4, 6, 2), (1, 3, 5)):
+        F, _, _ = _rand_case(Nt, Nd, Nm, seed=21)
+        x = np.random.default_rng(22).standard_normal((2, Nt, Nd))
+        A = _dense(F)
+        H = A @ A.T
+        got = oracle.hessian_data_space(F, x)
+        for b in range(2):
+            assert np.allclose(got[b].ravel(), H @ x[b].ravel(), rtol=1e-13, atol=1e-13)
+
+
+def test_hessian_symmetric_and_semidefinite():
+    F, _, _ = _rand_case(9, 4, 6, seed=23)
+    rng = np.random.default_rng(24)
+    x, y = rng.standard_normal((9, 4)), rng.standard_normal((9, 4))
+    Hx, Hy = oracle.hessian_data_space(F, x), oracle.hessian_data_space(F, y)
+    assert abs(np.vdot(Hx, y) - np.vdot(x, Hy)) <= 1e-12 * abs(np.vdot(Hx, y))
+    # <Hx, x> = ||F^T x||^2 >= 0, with F^T x as the dense transpose computes it
+    ft_x = _dense(F).T @ x.ravel()
+    assert abs(np.vdot(Hx, x) - ft_x @ ft_x) <= 1e-12 * (ft_x @ ft_x)
+
+
+def test_hessian_single_block_is_gram_matrix():
+    """Nt = 1: H = F_0 F_0^T, a plain Gram matrix."""
+    F, _, _ = _rand_case(1, 5, 7, seed=25)
+    x = np.random.default_rng(26).standard_normal((1, 5))
+    assert np.allclose(oracle.hessian_data_space(F, x)[0], F[0] @ (F[0].T @ x[0]), rtol=1e-14, atol=1e-14)
