@@ -171,21 +171,45 @@ ftm_status ftm_apply_scratch(ftm_operator op, int32_t adjoint, const double* x, 
 typedef enum ftm_rhs_mode { FTM_RHS_AUTO = 0, FTM_RHS_GEMV = 1, FTM_RHS_GEMM = 2 } ftm_rhs_mode;
 ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode);
 
-/* Smallest nrhs for which FTM_RHS_AUTO uses the GEMM (>= 2; default 2). */
+/* Smallest nrhs for which FTM_RHS_AUTO uses the GEMM (>= 2; default 2), for
+ * both directions and every storage format (ftm_set_tuning sets it per
+ * direction for the current configuration). */
 ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs);
 
-/* Autotuning of the phase-3 tile shape: time each of the matrix-vector
- * kernels' variants for both directions at the operator's current precision
- * configuration (one vector, reps timed runs each, on scratch inputs) and
- * keep the fastest.  Synchronises the stream.  The choice is kept per
- * direction and storage format; ftm_get_tuning / ftm_set_tuning read and set
- * it (for a persistent tuning cache kept by the caller).  Variants are
- * numbered 0 .. 3 per direction (0 is the default); other values are
- * FTM_ERR_INVALID. */
+/* Kernel and tile choices of one operator for its current precision
+ * configuration (the entries are kept per direction and per storage or
+ * compute format, so switching precision keeps each configuration's own).
+ *   gemv_variant[d]   matrix-vector tile of direction d (0 forward, 1
+ *                     adjoint): 0 .. 3, 0 the default
+ *   fft_shape[d][i]   transform kernel of direction d, i = 0 the input
+ *                     transform (phases 1-2), 1 the output one (4-5): 0 the
+ *                     default, 1 / 2 the fixed-plan kernels' larger / smaller
+ *                     column tile (lengths that have them: 128, 256, 400,
+ *                     512, 1024, 2000; others run the runtime-plan kernels
+ *                     whatever the value), 3 the runtime-plan kernels
+ *   gemm_tile[d]      right-hand sides per matrix-core GEMM tile: 0 (the
+ *                     default, 64), 16, 32 or 64
+ *   gemm_min_rhs[d]   smallest nrhs for which FTM_RHS_AUTO runs the GEMM (>= 2)
+ *   ms[d]             the matvec time (milliseconds) of the last autotune at
+ *                     these choices, 0 if none (read only) */
+typedef struct ftm_tuning {
+  int32_t gemv_variant[2];
+  int32_t fft_shape[2][2];
+  int32_t gemm_tile[2];
+  int64_t gemm_min_rhs[2];
+  double ms[2];
+} ftm_tuning;
+
+/* Autotuning (Section 3.1.1: tile parameters per precision, transition
+ * points from measurements): for both directions at the operator's current
+ * precision configuration, time the matrix-vector tile variants and the
+ * transform kernels on one vector (reps timed runs each, scratch inputs) and
+ * keep the fastest.  Synchronises the stream.  ftm_get_tuning /
+ * ftm_set_tuning read and set the choice (for a persistent tuning cache kept
+ * by the caller).  Out-of-range values are FTM_ERR_INVALID. */
 ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream);
-ftm_status ftm_get_tuning(ftm_operator op, int32_t* fwd_variant, int32_t* adj_variant, double* fwd_ms,
-                          double* adj_ms);
-ftm_status ftm_set_tuning(ftm_operator op, int32_t fwd_variant, int32_t adj_variant);
+ftm_status ftm_get_tuning(ftm_operator op, ftm_tuning* out);
+ftm_status ftm_set_tuning(ftm_operator op, const ftm_tuning* t);
 
 /* HIP graph of one matvec with fixed buffers (x, y as for ftm_matvec or
  * ftm_rmatvec; adjoint != 0 selects F^T).  Launching replays the three

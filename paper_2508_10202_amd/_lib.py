@@ -19,6 +19,8 @@ OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_BUDGET, ERR_HIP, ERR_STATE = rang
 F64, F32, F16, BF16 = range(4)
 # ftm_rhs_mode
 RHS_AUTO, RHS_GEMV, RHS_GEMM = range(3)
+# ftm_tuning.fft_shape: default, fixed-plan large / small tile, runtime-plan
+FFT_DEFAULT, FFT_FIXED, FFT_FIXED_SMALL, FFT_GENERIC = range(4)
 # ftm_gemv_type, ftm_gemv_op
 TYPE_S, TYPE_D, TYPE_C, TYPE_Z = range(4)
 OP_N, OP_T, OP_C = range(3)
@@ -40,6 +42,12 @@ EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec
 class FtmPrecision(ctypes.Structure):
     _fields_ = [("pad", ctypes.c_int32), ("fft", ctypes.c_int32), ("gemv", ctypes.c_int32),
                 ("ifft", ctypes.c_int32), ("unpad", ctypes.c_int32), ("accum", ctypes.c_int32)]
+
+
+class FtmTuning(ctypes.Structure):
+    _fields_ = [("gemv_variant", ctypes.c_int32 * 2), ("fft_shape", (ctypes.c_int32 * 2) * 2),
+                ("gemm_tile", ctypes.c_int32 * 2), ("gemm_min_rhs", ctypes.c_int64 * 2),
+                ("ms", ctypes.c_double * 2)]
 
 
 class FtmServerStats(ctypes.Structure):
@@ -85,9 +93,8 @@ def lib() -> ctypes.CDLL:
         "ftm_set_rhs_mode": [vp, i32],
         "ftm_set_gemm_crossover": [vp, i64],
         "ftm_autotune": [vp, i32, vp],
-        "ftm_get_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
-                           ctypes.POINTER(ctypes.c_double)],
-        "ftm_set_tuning": [vp, i32, i32],
+        "ftm_get_tuning": [vp, ctypes.POINTER(FtmTuning)],
+        "ftm_set_tuning": [vp, ctypes.POINTER(FtmTuning)],
         "ftm_graph_create": [ctypes.POINTER(vp), vp, i32, vp, vp, i64],
         "ftm_graph_launch": [vp, vp],
         "ftm_graph_destroy": [vp],

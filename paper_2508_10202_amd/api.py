@@ -11,7 +11,8 @@ import dataclasses
 import torch
 
 from . import _lib
-from ._lib import BF16, F16, F32, F64, OP_C, OP_N, OP_T, TYPE_C, TYPE_D, TYPE_S, TYPE_Z, FtmPrecision, check, lib
+from ._lib import (BF16, F16, F32, F64, OP_C, OP_N, OP_T, TYPE_C, TYPE_D, TYPE_S, TYPE_Z, FtmPrecision, FtmTuning,
+                   check, lib)
 
 _CODE = {"d": F64, "s": F32, "h": F16, "b": BF16}
 _CHAR = {v: k for k, v in _CODE.items()}
@@ -251,8 +252,7 @@ class Operator:
             with open(cache) as fh:
                 db = json.load(fh)
         if key in db:
-            check(lib().ftm_set_tuning(self.handle, db[key]["fwd_variant"], db[key]["adj_variant"]),
-                  "ftm_set_tuning")
+            self.set_tuning(**{k: v for k, v in db[key].items() if k != "ms"})
             return dict(db[key], cached=True)
         with torch.cuda.device(self.device):
             check(lib().ftm_autotune(self.handle, int(reps), _stream_ptr(stream)), "ftm_autotune")
@@ -266,14 +266,30 @@ class Operator:
         return dict(rec, cached=False)
 
     def tuning(self) -> dict:
-        fv, av = ctypes.c_int32(), ctypes.c_int32()
-        fm, am = ctypes.c_double(), ctypes.c_double()
-        check(lib().ftm_get_tuning(self.handle, ctypes.byref(fv), ctypes.byref(av), ctypes.byref(fm),
-                                   ctypes.byref(am)), "ftm_get_tuning")
-        return {"fwd_variant": fv.value, "adj_variant": av.value, "fwd_ms": fm.value, "adj_ms": am.value}
+        """The kernel and tile choices for the current precision (``ftm_get_tuning``):
+        per direction [forward, adjoint] the product's tile variant, the input
+        and output transforms' kernels, the GEMM tile, the GEMM crossover and
+        the autotuned matvec time."""
+        t = FtmTuning()
+        check(lib().ftm_get_tuning(self.handle, ctypes.byref(t)), "ftm_get_tuning")
+        return {"gemv_variant": list(t.gemv_variant), "fft_shape": [list(r) for r in t.fft_shape],
+                "gemm_tile": list(t.gemm_tile), "gemm_min_rhs": list(t.gemm_min_rhs), "ms": list(t.ms)}
 
-    def set_tuning(self, fwd_variant: int, adj_variant: int) -> None:
-        check(lib().ftm_set_tuning(self.handle, int(fwd_variant), int(adj_variant)), "ftm_set_tuning")
+    def set_tuning(self, gemv_variant=None, fft_shape=None, gemm_tile=None, gemm_min_rhs=None) -> None:
+        """Set some of the choices (``ftm_set_tuning``); each argument is a
+        [forward, adjoint] pair (``fft_shape``: a pair of [input, output])."""
+        t = FtmTuning()
+        check(lib().ftm_get_tuning(self.handle, ctypes.byref(t)), "ftm_get_tuning")
+        for d in range(2):
+            if gemv_variant is not None:
+                t.gemv_variant[d] = int(gemv_variant[d])
+            if fft_shape is not None:
+                t.fft_shape[d][0], t.fft_shape[d][1] = int(fft_shape[d][0]), int(fft_shape[d][1])
+            if gemm_tile is not None:
+                t.gemm_tile[d] = int(gemm_tile[d])
+            if gemm_min_rhs is not None:
+                t.gemm_min_rhs[d] = int(gemm_min_rhs[d])
+        check(lib().ftm_set_tuning(self.handle, ctypes.byref(t)), "ftm_set_tuning")
 
     def graph(self, x: torch.Tensor, adjoint: bool = False, out=None) -> "Graph":
         """Capture one matvec with fixed buffers into a HIP graph (``ftm_graph_create``)."""

@@ -1,6 +1,6 @@
 """Compile the HIP library ``libftm.so`` in-tree for gfx950 with hipcc.
 
-Every call recompiles (three translation units in parallel) and then
+Every call recompiles (the translation units in parallel) and then
 atomically replaces ``paper_2508_10202_amd/libftm.so``.  Objects go to
 ``_build/`` at the repository root.
 """
@@ -16,6 +16,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libftm.so")
 SOURCES = ("ftm_api.hip", "ftm_fft.hip", "ftm_gemv.hip", "ftm_gemm.hip", "ftm_server.hip", "ftm_sbgemv.hip")
+# ftm_fft_fixed.hip is compiled once per transform length with a fixed plan;
+# the list matches FTM_FIXED_LENGTHS in ftm_fft.hip.
+FIXED_SRC = "ftm_fft_fixed.hip"
+FIXED_LENGTHS = (128, 256, 400, 512, 1024, 2000)
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are switched off for every device compile; hipcc's
@@ -48,7 +52,12 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         jobs.append((obj, [cc, *COMMON_FLAGS, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]))
-    with concurrent.futures.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+    for n in FIXED_LENGTHS:
+        obj = os.path.join(bdir, f"ftm_fft_fixed_{n}.o")
+        jobs.append((obj, [cc, *COMMON_FLAGS, *DEVICE_FLAGS, f"-DFTM_FIXED_N={n}", "-c",
+                           os.path.join(CSRC, FIXED_SRC), "-o", obj]))
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
         for fut in [ex.submit(_run, cmd) for _, cmd in jobs]:
             fut.result()
     tmp = LIB_PATH + ".tmp"

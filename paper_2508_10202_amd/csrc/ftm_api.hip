@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -55,9 +56,13 @@ ftm_rt::Exec ftm_operator_s::exec(bool adjoint, int64_t nrhs, bool allow_profile
   ftm_rt::Exec e;
   e.p = adjoint ? adj : fwd;
   e.gemv_variant = variant[adjoint ? 1 : 0][e.p.gemv];
+  e.fft_shape_in = fft_shape[adjoint ? 1 : 0][0][e.p.fft == ftm::DT_F64 ? 1 : 0];
+  e.fft_shape_out = fft_shape[adjoint ? 1 : 0][1][e.p.ifft == ftm::DT_F64 ? 1 : 0];
+  e.gemm_tile = gemm_tile[adjoint ? 1 : 0][e.p.gemv];
   // many right-hand sides: one pass of the spectrum through the matrix cores
   const bool gemm_ok = e.p.gemv != ftm::DT_F64 && e.p.accum != ftm::DT_F64 && nrhs >= 2;
-  e.use_gemm = gemm_ok && (rhs_mode == FTM_RHS_GEMM || (rhs_mode == FTM_RHS_AUTO && nrhs >= gemm_min_rhs));
+  e.use_gemm = gemm_ok && (rhs_mode == FTM_RHS_GEMM ||
+                           (rhs_mode == FTM_RHS_AUTO && nrhs >= gemm_min_rhs[adjoint ? 1 : 0][e.p.gemv]));
   e.profile = allow_profile && profiling;
   return e;
 }
@@ -89,14 +94,25 @@ ftm_status check_precision(const ftm_precision& p) {
 
 const ftm_precision kAllF64 = {DT_F64, DT_F64, DT_F64, DT_F64, DT_F64, DT_F64};
 
-// Radices of a length-N plan: the factor 2^e2 in as few passes as radices up to
-// 2^maxbits allow, its bits spread evenly over them (larger radices first),
-// then 5, 3 and 7.  float32 transforms take radix 16 (maxbits 4); float64
-// ones stop at radix 8, whose registers leave room for more waves per SIMD.
-#ifndef FTM_FFT_RADIX16
-#define FTM_FFT_RADIX16 1
-#endif
-bool make_plan(int N, int maxbits, FftPlan* plan) {
+// Radices of length-N plans: the factor 2^e2 in as few passes as radices up
+// to 2^maxbits allow, its bits spread evenly over them, then the factors 5, 3
+// and 7; in
+// descending order for the forward transform (its paired last pass takes the
+// smallest radix) and ascending for the inverse one (paired first pass).  At
+// least two passes: a lone power of two is split, and N = 2 runs 2 and 1.
+void fill_plan(int N, const std::vector<int>& rad, FftPlan* plan) {
+  plan->N = N;
+  plan->nst = (int)rad.size();
+  int Ns = 1;
+  for (int i = 0; i < plan->nst; ++i) {
+    plan->rad[i] = rad[i];
+    plan->toff[i] = Ns == 1 && i == 0 ? 0 : plan->toff[i - 1] + Ns;  // pass i-1 took Ns = Ns_{i-1} * rad[i-1] entries
+    plan->div_ns[i] = make_fastdiv((uint32_t)Ns);
+    Ns *= rad[i];
+  }
+}
+
+bool make_plans(int N, int maxbits, FftPlan* fwd, FftPlan* inv) {
   int n = N, e2 = 0;
   std::vector<int> rad;
   while (n % 2 == 0) { n /= 2; ++e2; }
@@ -108,16 +124,20 @@ bool make_plan(int N, int maxbits, FftPlan* plan) {
   }
   for (int r : {5, 3, 7})
     while (n % r == 0) { n /= r; rad.push_back(r); }
-  if (n != 1 || (int)rad.size() > MAX_STAGES) return false;
-  plan->N = N;
-  plan->nst = (int)rad.size();
-  int Ns = 1;
-  for (int i = 0; i < plan->nst; ++i) {
-    plan->rad[i] = rad[i];
-    plan->toff[i] = Ns == 1 ? 0 : plan->toff[i - 1] + Ns;  // pass i-1 took Ns = Ns_{i-1} * rad[i-1] entries
-    plan->div_ns[i] = make_fastdiv((uint32_t)Ns);
-    Ns *= rad[i];
+  if (n != 1 || rad.empty()) return false;
+  if (rad.size() == 1) {
+    const int r = rad[0];
+    if (r == 2) rad = {2, 1};
+    else if (r == 4) rad = {2, 2};
+    else if (r == 8) rad = {4, 2};
+    else if (r == 16) rad = {4, 4};
+    else return false;
   }
+  if ((int)rad.size() > MAX_STAGES) return false;
+  std::sort(rad.begin(), rad.end(), [](int a, int b) { return a > b; });
+  fill_plan(N, rad, fwd);
+  std::reverse(rad.begin(), rad.end());
+  fill_plan(N, rad, inv);
   return true;
 }
 
@@ -149,8 +169,11 @@ void release(ftm_operator op) {
   op->recs.clear();
   for (hipEvent_t e : op->event_pool) (void)hipEventDestroy(e);
   op->event_pool.clear();
-  dev_free(&op->tw64);
-  dev_free(&op->tw32);
+  dev_free(&op->tw64f);
+  dev_free(&op->tw64i);
+  dev_free(&op->tw32f);
+  dev_free(&op->tw32i);
+  dev_free(&op->twg64);
   for (auto& s : op->spec) dev_free(&s);
   dev_free(&op->mhat);
   dev_free(&op->dhat);
@@ -177,15 +200,22 @@ std::vector<T> twiddle_table(const FftPlan& pl) {
   return t;
 }
 
-// float64 transforms run op->plan, float32 ones op->plan32.
+// Twiddle tables of the plans in their compute types.
 ftm_status upload_twiddles(ftm_operator op, hipStream_t st) {
-  const std::vector<double> t64 = twiddle_table<double>(op->plan);
-  const std::vector<float> t32 = twiddle_table<float>(op->plan32);
+  const std::vector<double> t64f = twiddle_table<double>(op->plan_f), t64i = twiddle_table<double>(op->plan_i);
+  const std::vector<float> t32f = twiddle_table<float>(op->plan_f), t32i = twiddle_table<float>(op->plan_i);
+  const std::vector<double> tg64 = twiddle_table<double>(op->plan_g64);
   ftm_status s;
-  if ((s = dev_alloc(&op->tw64, t64.size() * sizeof(double))) != FTM_OK) return s;
-  if ((s = dev_alloc(&op->tw32, t32.size() * sizeof(float))) != FTM_OK) return s;
-  FTM_HIP(hipMemcpyAsync(op->tw64.p, t64.data(), op->tw64.n, hipMemcpyHostToDevice, st));
-  FTM_HIP(hipMemcpyAsync(op->tw32.p, t32.data(), op->tw32.n, hipMemcpyHostToDevice, st));
+  if ((s = dev_alloc(&op->twg64, tg64.size() * sizeof(double))) != FTM_OK) return s;
+  FTM_HIP(hipMemcpyAsync(op->twg64.p, tg64.data(), op->twg64.n, hipMemcpyHostToDevice, st));
+  if ((s = dev_alloc(&op->tw64f, t64f.size() * sizeof(double))) != FTM_OK) return s;
+  if ((s = dev_alloc(&op->tw64i, t64i.size() * sizeof(double))) != FTM_OK) return s;
+  if ((s = dev_alloc(&op->tw32f, t32f.size() * sizeof(float))) != FTM_OK) return s;
+  if ((s = dev_alloc(&op->tw32i, t32i.size() * sizeof(float))) != FTM_OK) return s;
+  FTM_HIP(hipMemcpyAsync(op->tw64f.p, t64f.data(), op->tw64f.n, hipMemcpyHostToDevice, st));
+  FTM_HIP(hipMemcpyAsync(op->tw64i.p, t64i.data(), op->tw64i.n, hipMemcpyHostToDevice, st));
+  FTM_HIP(hipMemcpyAsync(op->tw32f.p, t32f.data(), op->tw32f.n, hipMemcpyHostToDevice, st));
+  FTM_HIP(hipMemcpyAsync(op->tw32i.p, t32i.data(), op->tw32i.n, hipMemcpyHostToDevice, st));
   // the host vectors die at return: make the copies complete first
   FTM_HIP(hipStreamSynchronize(st));
   return FTM_OK;
@@ -277,10 +307,9 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ra.r_pad = p.pad;
   ra.r_fft = p.fft;
   ra.r_next = p.gemv;
-  const void* tw_in = p.fft == DT_F64 ? op->tw64.p : op->tw32.p;
   Profiler prof(op, st, adjoint ? 1 : 0, ex.profile);
   prof.mark(0);
-  FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, p.fft == DT_F64 ? op->plan : op->plan32, tw_in, st));
+  FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, op->fft_in(p.fft == DT_F64), ex.fft_shape_in, st));
 
   GemvArgs ga{};
   ga.F = F;
@@ -323,9 +352,8 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ia.y_row_stride = Sy;
   ia.r_ifft = p.ifft;
   ia.r_unpad = p.unpad;
-  const void* tw_out = p.ifft == DT_F64 ? op->tw64.p : op->tw32.p;
   prof.mark(2);
-  FTM_HIP(launch_irfft(y_hat64, p.ifft == DT_F64, ia, p.ifft == DT_F64 ? op->plan : op->plan32, tw_out, st));
+  FTM_HIP(launch_irfft(y_hat64, p.ifft == DT_F64, ia, op->fft_out(p.ifft == DT_F64), ex.fft_shape_out, st));
   prof.mark(3);
   return FTM_OK;
 }
@@ -402,8 +430,8 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     ftm_status s;
     if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
 
-    FftPlan plan{}, plan32{};
-    if (!make_plan((int)L, 3, &plan) || !make_plan((int)L, FTM_FFT_RADIX16 ? 4 : 3, &plan32))
+    FftPlan plan_f{}, plan_i{}, plan_g64{}, unused{};
+    if (!make_plans((int)L, 4, &plan_f, &plan_i) || !make_plans((int)L, 3, &plan_g64, &unused))
       return fail(FTM_ERR_UNSUPPORTED, "no FFT plan for L = " + std::to_string(L));
 
     ftm_operator op = new ftm_operator_s();
@@ -415,8 +443,9 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     op->ldm = (int)((Nm + 7) / 8 * 8);
     op->ldd = (int)((Nd + 7) / 8 * 8);
     op->max_rhs = max_rhs;
-    op->plan = plan;
-    op->plan32 = plan32;
+    op->plan_f = plan_f;
+    op->plan_i = plan_i;
+    op->plan_g64 = plan_g64;
     op->fwd = pf;
     op->adj = pa;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -448,7 +477,7 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     ra.ld_row = op->ldm;
     ra.r_pad = ra.r_fft = ra.r_next = DT_F64;
     ra.pad_to = 0;  // the spectrum's padding is cleared above
-    e = launch_rfft(true, true, ra, op->plan, op->tw64.p, st);
+    e = launch_rfft(true, true, ra, op->fft_in(true), 0, st);
     if (e != hipSuccess) return bail(fail_hip("setup transform", e));
 
     const uint32_t keep = needed_mask(pf, pa) | spectra;
@@ -660,7 +689,8 @@ ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs) {
   if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
   if (min_rhs < 2) return fail(FTM_ERR_INVALID, "the crossover is at least 2 right-hand sides");
   std::lock_guard<std::mutex> lk(op->mu);
-  op->gemm_min_rhs = min_rhs;
+  for (auto& d : op->gemm_min_rhs)
+    for (auto& v : d) v = min_rhs;
   return FTM_OK;
 }
 
@@ -733,58 +763,101 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
   ftm_rt::Workspace ws;
   ws.mhat = op->mhat.p;
   ws.dhat = op->dhat.p;
-  int best_v[2] = {0, 0};
-  double best_t[2] = {1e300, 1e300};
-  ftm_rt::Exec ex[2];
+  ftm_rt::MatvecIO io;
+  io.x = reinterpret_cast<const double*>(x.p);
+  io.y = reinterpret_cast<double*>(y.p);
+  // time one configuration: one warm call, then reps timed calls
+  auto time_exec = [&](bool adj, const ftm_rt::Exec& ex, double* ms) -> ftm_status {
+    ftm_status r = ftm_rt::run_matvec(op, adj, ex, io, 1, ws, st);
+    if (r != FTM_OK) return r;
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i) ftm_rt::run_matvec(op, adj, ex, io, 1, ws, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(FTM_ERR_HIP, "hipEventSynchronize");
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    *ms = t / reps;
+    return FTM_OK;
+  };
+  // coordinate search per direction: the product's tile, then the input and
+  // the output transform's kernel, each with the others at their best so far
+  ftm_rt::Exec best[2];
+  double best_t[2] = {0.0, 0.0};
+  const bool fixed = fft_has_fixed((int)op->L);
   for (int dir = 0; dir < 2; ++dir) {
-    ex[dir] = op->exec(dir == 1, 1, false);
-    ftm_rt::MatvecIO io;
-    io.x = reinterpret_cast<const double*>(x.p);
-    io.y = reinterpret_cast<double*>(y.p);
+    ftm_rt::Exec ex = op->exec(dir == 1, 1, false);
+    ex.use_gemm = false;
+    double bt = 1e300;
+    ftm_rt::Exec b = ex;
     for (int v = 0; v < GEMV_VARIANTS; ++v) {
-      ex[dir].gemv_variant = v;
-      if ((s = ftm_rt::run_matvec(op, dir == 1, ex[dir], io, 1, ws, st)) != FTM_OK) return done(s);
-      (void)hipEventRecord(e0, st);
-      for (int r = 0; r < reps; ++r) ftm_rt::run_matvec(op, dir == 1, ex[dir], io, 1, ws, st);
-      (void)hipEventRecord(e1, st);
-      if (hipEventSynchronize(e1) != hipSuccess) return done(fail(FTM_ERR_HIP, "hipEventSynchronize"));
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms / reps < best_t[dir]) {
-        best_t[dir] = ms / reps;
-        best_v[dir] = v;
-      }
+      ex.gemv_variant = v;
+      double t;
+      if ((s = time_exec(dir == 1, ex, &t)) != FTM_OK) return done(s);
+      if (t < bt) { bt = t; b = ex; }
     }
+    ex = b;
+    for (int side = 0; side < 2; ++side) {
+      for (int sh = fixed ? 1 : FFT_SHAPE_GENERIC; sh < FFT_SHAPES; ++sh) {
+        (side == 0 ? ex.fft_shape_in : ex.fft_shape_out) = sh;
+        double t;
+        if ((s = time_exec(dir == 1, ex, &t)) != FTM_OK) return done(s);
+        if (t < bt) { bt = t; b = ex; }
+      }
+      ex = b;
+    }
+    best[dir] = b;
+    best_t[dir] = bt;
   }
   {
-    // keep the winners for the storage formats they were timed with
+    // keep the winners for the formats they were timed with
     std::lock_guard<std::mutex> lk(op->mu);
     for (int dir = 0; dir < 2; ++dir) {
-      op->variant[dir][ex[dir].p.gemv] = best_v[dir];
+      const ftm_precision& p = best[dir].p;
+      op->variant[dir][p.gemv] = best[dir].gemv_variant;
+      op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0] = best[dir].fft_shape_in;
+      op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0] = best[dir].fft_shape_out;
       op->tuned_ms[dir] = best_t[dir];
     }
   }
   return done(FTM_OK);
 }
 
-ftm_status ftm_get_tuning(ftm_operator op, int32_t* fwd_variant, int32_t* adj_variant, double* fwd_ms,
-                          double* adj_ms) {
-  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+ftm_status ftm_get_tuning(ftm_operator op, ftm_tuning* out) {
+  if (!op || !out) return fail(FTM_ERR_INVALID, "operator or out is NULL");
   std::lock_guard<std::mutex> lk(op->mu);
-  if (fwd_variant) *fwd_variant = op->variant[0][op->fwd.gemv];
-  if (adj_variant) *adj_variant = op->variant[1][op->adj.gemv];
-  if (fwd_ms) *fwd_ms = op->tuned_ms[0];
-  if (adj_ms) *adj_ms = op->tuned_ms[1];
+  for (int dir = 0; dir < 2; ++dir) {
+    const ftm_precision& p = dir ? op->adj : op->fwd;
+    out->gemv_variant[dir] = op->variant[dir][p.gemv];
+    out->fft_shape[dir][0] = op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0];
+    out->fft_shape[dir][1] = op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0];
+    out->gemm_tile[dir] = op->gemm_tile[dir][p.gemv];
+    out->gemm_min_rhs[dir] = op->gemm_min_rhs[dir][p.gemv];
+    out->ms[dir] = op->tuned_ms[dir];
+  }
   return FTM_OK;
 }
 
-ftm_status ftm_set_tuning(ftm_operator op, int32_t fwd_variant, int32_t adj_variant) {
-  if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
-  if (fwd_variant < 0 || fwd_variant >= GEMV_VARIANTS || adj_variant < 0 || adj_variant >= GEMV_VARIANTS)
-    return fail(FTM_ERR_INVALID, "variant out of range");
+ftm_status ftm_set_tuning(ftm_operator op, const ftm_tuning* t) {
+  if (!op || !t) return fail(FTM_ERR_INVALID, "operator or tuning is NULL");
+  for (int dir = 0; dir < 2; ++dir) {
+    if (t->gemv_variant[dir] < 0 || t->gemv_variant[dir] >= GEMV_VARIANTS)
+      return fail(FTM_ERR_INVALID, "gemv_variant out of range");
+    for (int side = 0; side < 2; ++side)
+      if (t->fft_shape[dir][side] < 0 || t->fft_shape[dir][side] >= FFT_SHAPES)
+        return fail(FTM_ERR_INVALID, "fft_shape out of range");
+    const int gt = t->gemm_tile[dir];
+    if (gt != 0 && gt != 16 && gt != 32 && gt != 64) return fail(FTM_ERR_INVALID, "gemm_tile must be 0, 16, 32 or 64");
+    if (t->gemm_min_rhs[dir] < 2) return fail(FTM_ERR_INVALID, "gemm_min_rhs must be >= 2");
+  }
   std::lock_guard<std::mutex> lk(op->mu);
-  op->variant[0][op->fwd.gemv] = fwd_variant;
-  op->variant[1][op->adj.gemv] = adj_variant;
+  for (int dir = 0; dir < 2; ++dir) {
+    const ftm_precision& p = dir ? op->adj : op->fwd;
+    op->variant[dir][p.gemv] = t->gemv_variant[dir];
+    op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0] = t->fft_shape[dir][0];
+    op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0] = t->fft_shape[dir][1];
+    op->gemm_tile[dir][p.gemv] = t->gemm_tile[dir];
+    op->gemm_min_rhs[dir][p.gemv] = t->gemm_min_rhs[dir];
+  }
   return FTM_OK;
 }
 

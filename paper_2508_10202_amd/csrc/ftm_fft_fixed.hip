@@ -1,0 +1,587 @@
+// Batched real FFTs over time (phases 1+2 and 4+5) for transform lengths
+// whose plan is fixed at compile time, for gfx950.  This file is compiled once
+// per length N (FTM_FIXED_N); ftm_fft.hip dispatches to it when the operator's
+// plan is the one compiled here and runs the runtime-plan kernels otherwise.
+//
+// Two real series (adjacent columns) share one complex transform of length N,
+// one as the real part and one as the imaginary part, and are separated with
+// the conjugate symmetry of real spectra.  Each transform is a self-sorting
+// mixed-radix Stockham FFT (Govindaraju et al., SC'08) run by T threads:
+// every pass reads R points at stride N/R, applies the twiddles, does an
+// R-point DFT in registers and writes the R results in sorted order.  With
+// the plan fixed, every stride, butterfly count and twiddle offset is a
+// constant.  The passes exchange data through the transform's own LDS slab;
+// when a transform fits in one wave (T <= 64) the exchanges rely on the
+// wave's in-order LDS accesses and need no workgroup barrier.
+//
+// A workgroup owns a tile of C adjacent columns (C/2 transforms).  It loads
+// the tile's rows t < Nt with coalesced row segments into the transforms'
+// slabs, and writes the tile's output rows the same way from the slabs, so
+// every global access moves whole C-column row segments; in between, each
+// transform runs its passes on its own slab.  The forward transform's first
+// pass never reads the zero padding (inputs that can only be padding are
+// zero constants), and its last pass pairs the butterflies j and N/R - j in
+// one thread, so that the bins k and N - k that the separation combines meet
+// in registers.  The inverse transform mirrors it: its first pass pairs
+// butterflies so that each stored bin fills both its own slot and its
+// mirror's (the Hermitian extension).  The forward plan lists its radices in
+// descending order and the inverse plan in ascending order, so the paired
+// passes take the smallest radix.  Twiddles come from the operator's per-pass
+// tables (long double on the host, rounded once).
+#include "ftm_device.h"
+#include "ftm_dft.h"
+#include "ftm_kernels.h"
+
+#ifndef FTM_FIXED_N
+#error "compile with -DFTM_FIXED_N=<transform length>"
+#endif
+
+namespace ftm {
+namespace {
+
+// LDS slot of complex element i of a slab: the XOR of the low 4 bits with the
+// 16-element group index spreads the strided writes of the early passes over
+// the banks; it permutes each group of 16, so a slab is N rounded up to 16.
+__device__ __forceinline__ int lds_ix(int i) { return i ^ ((i >> 4) & 15); }
+constexpr int lds_size(int n) { return (n + 15) / 16 * 16; }
+
+// A plan fixed at compile time: passes of radix Rs... (product N).  Pass s
+// runs after Ns(s) = rad[0] * .. * rad[s-1] points are combined and reads its
+// twiddles exp(-2 pi i q jm / (Ns R)) at toff(s) + jm R + q of the operator's
+// table for this plan.
+template <int... Rs>
+struct CPlan {
+  static constexpr int nst = sizeof...(Rs);
+  static constexpr int rad[nst] = {Rs...};
+  static constexpr int N = (Rs * ...);
+  static constexpr int ns(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= rad[i];
+    return p;
+  }
+  static constexpr int toff(int s) {
+    int o = 0;
+    for (int i = 0; i < s; ++i) o += ns(i + 1);
+    return o;
+  }
+};
+
+// Order the LDS accesses of the threads of one transform: a wave-level fence
+// when the transform lives in one wave (its LDS accesses complete in issue
+// order), a workgroup barrier otherwise.
+template <int T>
+__device__ __forceinline__ void tsync() {
+  if constexpr (T <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// A middle pass S of plan P: butterfly j = lane + i T < N/R reads points
+// j + q N/R, twiddles them, and writes its DFT to (j - jm) R + jm + q Ns with
+// jm = j mod Ns.  All reads precede all writes (the pass works in place).
+template <class P, int S, int T, class TC>
+__device__ __forceinline__ void mid_pass(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw) {
+  constexpr int R = P::rad[S], NS = P::ns(S), nb = P::N / R, MB = (nb + T - 1) / T;
+  const cplx<TC>* tws = tw + P::toff(S);
+  cplx<TC> v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int j = lane + i * T;
+    if (nb % T == 0 || j < nb) {
+      const int jm = j % NS;
+      v[i][0] = lds[lds_ix(j)];
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(j + q * nb)], tws[jm * R + q]);
+    }
+  }
+  tsync<T>();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int j = lane + i * T;
+    if (nb % T == 0 || j < nb) {
+      dft<R>(v[i]);
+      const int jm = j % NS, dst = (j - jm) * R + jm;
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[lds_ix(dst + q * NS)] = v[i][q];
+    }
+  }
+  tsync<T>();
+}
+
+template <class P, int S, int T, class TC>
+__device__ __forceinline__ void mid_passes(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw) {
+  if constexpr (S + 1 < P::nst) {
+    mid_pass<P, S, T>(lds, lane, tw);
+    mid_passes<P, S + 1, T>(lds, lane, tw);
+  }
+}
+
+// Which butterflies a paired unit u (0 <= u <= N/(2R)) of a pass with nb = N/R
+// butterflies holds: kind 0 butterfly 0 alone (the partner of its output q is
+// its output (R - q) mod R), kind 1 butterfly nb/2 alone (partner R-1-q),
+// kind 2 butterflies u and nb - u (partner R-1-q of the other one).
+__device__ __forceinline__ int unit_kind(int u, int nb) { return u == 0 ? 0 : (2 * u == nb ? 1 : 2); }
+
+// ---- phases 1+2: pad (+round) + real FFT -------------------------------------
+
+// First pass from the slab, where the tile load left rows t < Nt.  As
+// L >= 2 Nt, only q < (R + 1) / 2 can reach such a row: the other inputs are
+// zero constants.  In place: all reads precede all writes.
+template <class P, int T, class TC>
+__device__ __forceinline__ void rfft_first(cplx<TC>* lds, int Nt, int lane) {
+  constexpr int R = P::rad[0], nb = P::N / R, MB = (nb + T - 1) / T, QL = (R + 1) / 2;
+  static_assert(QL * nb >= P::N / 2, "inputs below N/2 reach a pruned slot");
+  cplx<TC> v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int j = lane + i * T;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      v[i][q] = {(TC)0, (TC)0};
+      if (q < QL && (nb % T == 0 || j < nb) && j + q * nb < Nt) v[i][q] = lds[lds_ix(j + q * nb)];
+    }
+  }
+  tsync<T>();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int j = lane + i * T;
+    if (nb % T == 0 || j < nb) {
+      dft<R>(v[i]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[lds_ix(j * R + q)] = v[i][q];
+    }
+  }
+  tsync<T>();
+}
+
+// Bin k of both real series from Z_k and Z_{N-k}, rounded to the FFT format
+// and then to the next phase's: X = (Z_k + conj Z_{N-k}) / 2 goes to slab
+// slot k, Y = (Z_k - conj Z_{N-k}) / 2i to slot N/2 + 1 + k.
+template <bool HALF, int N, class TC>
+__device__ __forceinline__ void sep_bin(cplx<TC>* lds, int k, cplx<TC> zk, cplx<TC> zr, int r_fft, int r_next) {
+  cplx<TC> X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
+  cplx<TC> Y = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
+  lds[lds_ix(k)] = round_as<HALF>(round_as<HALF>(X, r_fft), r_next);
+  lds[lds_ix(N / 2 + 1 + k)] = round_as<HALF>(round_as<HALF>(Y, r_fft), r_next);
+}
+
+// Last pass (Ns = nb, so jm = j) with butterflies j and nb - j in one thread;
+// the separated bins k <= N/2 of both series replace the transform in its
+// slab.  All reads precede all writes.
+template <class P, int T, bool HALF, class TC>
+__device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw, int r_fft,
+                                          int r_next) {
+  constexpr int S = P::nst - 1, R = P::rad[S], N = P::N, nb = N / R, nu = nb / 2 + 1, hN = N / 2;
+  constexpr int MU = (nu + T - 1) / T;
+  const cplx<TC>* tws = tw + P::toff(S);
+  cplx<TC> v1[MU][R], v2[MU][R];
+#pragma unroll
+  for (int i = 0; i < MU; ++i) {
+    const int u = lane + i * T;
+    if (nu % T != 0 && u >= nu) continue;
+    const int j1 = u, j2 = nb - u;
+    v1[i][0] = lds[lds_ix(j1)];
+#pragma unroll
+    for (int q = 1; q < R; ++q) v1[i][q] = cmul(lds[lds_ix(j1 + q * nb)], tws[j1 * R + q]);
+    if (unit_kind(u, nb) == 2) {
+      v2[i][0] = lds[lds_ix(j2)];
+#pragma unroll
+      for (int q = 1; q < R; ++q) v2[i][q] = cmul(lds[lds_ix(j2 + q * nb)], tws[j2 * R + q]);
+    }
+  }
+  tsync<T>();
+#pragma unroll
+  for (int i = 0; i < MU; ++i) {
+    const int u = lane + i * T;
+    if (nu % T != 0 && u >= nu) continue;
+    const int kind = unit_kind(u, nb), j1 = u, j2 = nb - u;
+    dft<R>(v1[i]);
+    if (kind == 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (q * nb <= hN) sep_bin<HALF, N>(lds, q * nb, v1[i][q], v1[i][(R - q) % R], r_fft, r_next);
+    } else if (kind == 1) {
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (j1 + q * nb <= hN) sep_bin<HALF, N>(lds, j1 + q * nb, v1[i][q], v1[i][R - 1 - q], r_fft, r_next);
+    } else {
+      dft<R>(v2[i]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if (j1 + q * nb <= hN) sep_bin<HALF, N>(lds, j1 + q * nb, v1[i][q], v2[i][R - 1 - q], r_fft, r_next);
+        if (j2 + q * nb <= hN) sep_bin<HALF, N>(lds, j2 + q * nb, v2[i][q], v1[i][R - 1 - q], r_fft, r_next);
+      }
+    }
+  }
+}
+
+// Slab of transform `slot`: N + 2 complex values (the separated bins of both
+// series need N + 2), rounded up to 16.
+template <int N>
+constexpr int slab_size() { return lds_size(N + 2); }
+
+// A tile of C columns (C/2 transforms of T threads) per workgroup.
+template <class P, class TC, class TO, bool HALF, int T, int C>
+__global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const cplx<TC>* __restrict__ tw,
+                                                               int64_t ntile) {
+  constexpr int N = P::N, WG = C / 2 * T, SL = slab_size<N>(), ROWS = WG / C;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<TC>* slabs = reinterpret_cast<cplx<TC>*>(smem_raw);
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t b = wg / ntile, s0 = (wg - b * ntile) * C;
+  const int tid = threadIdx.x, Nt = a.Nt;
+
+  // tile load: thread tid takes column c = tid mod C of rows tid / C + n ROWS;
+  // both series of a transform share its slab (real and imaginary parts)
+  {
+    const int c = tid % C;
+    const bool live = s0 + c < a.S;
+    const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
+    const double* xs = xb + (live ? s0 + c : 0);
+    TC* comp = reinterpret_cast<TC*>(slabs + (c / 2) * SL) + (c & 1);
+    constexpr int U = 4;  // loads in flight per thread
+    for (int t0 = tid / C; t0 < Nt; t0 += U * ROWS) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * ROWS;
+        v[u] = (live && t < Nt) ? xs[(int64_t)t * a.x_row_stride] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * ROWS;
+        if (t < Nt) comp[2 * lds_ix(t)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), a.r_fft);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int slot = tid / T, lane = tid % T;
+    cplx<TC>* lds = slabs + slot * SL;
+    rfft_first<P, T>(lds, Nt, lane);
+    mid_passes<P, 1, T>(lds, lane, tw);
+    rfft_last<P, T, HALF>(lds, lane, tw, a.r_fft, a.r_next);
+  }
+  __syncthreads();
+  // tile store: bins k <= N/2 of column c; columns S .. pad_to-1 of the last
+  // tile are the padding the products read (times the spectrum's zero
+  // padding) and are written as zeros
+  {
+    const int c = tid % C;
+    const int64_t s = s0 + c;
+    if (s >= a.S && s >= a.pad_to) return;
+    const cplx<TC>* slab = slabs + (c / 2) * SL;
+    const int off = (c & 1) ? N / 2 + 1 : 0;
+    cplx<TO>* o;
+    if (s < a.S) {
+      // one output row per right-hand side, or (the setup transform) row
+      // s / ncol of a [Nd][ld_row] block per bin
+      const int64_t row = a.ncol >= a.S ? 0 : s / a.ncol;
+      o = reinterpret_cast<cplx<TO>*>(a.out) + b * a.out_rhs_stride + row * a.ld_row + (s - row * a.ncol);
+    } else {
+      o = reinterpret_cast<cplx<TO>*>(a.out) + b * a.out_rhs_stride + s;
+    }
+    const bool pad = s >= a.S;
+    for (int k = tid / C; k <= N / 2; k += ROWS) {
+      cplx<TO> w = {(TO)0, (TO)0};
+      if (!pad) {
+        const cplx<TC> z = slab[lds_ix(off + k)];
+        w = {(TO)z.x, (TO)z.y};
+      }
+      o[(int64_t)k * a.out_k_stride] = w;
+    }
+  }
+}
+
+// ---- phases 4+5: inverse real FFT + scale + unpad ---------------------------
+
+// conj of the Hermitian extension Z = A + iB at a stored bin k (direct) and at
+// bin N - k (mirror): the inverse transform is conj(FFT(conj Z)) / N.
+template <class TC>
+__device__ __forceinline__ cplx<TC> conj_z_direct(cplx<TC> A, cplx<TC> B) { return {A.x - B.y, -(A.y + B.x)}; }
+template <class TC>
+__device__ __forceinline__ cplx<TC> conj_z_mirror(cplx<TC> A, cplx<TC> B) { return {A.x + B.y, A.y - B.x}; }
+
+// First pass (Ns = 1, no twiddles) from the bins the tile load left in the
+// slab (series s at slot k, series s + 1 at slot N/2 + 1 + k), butterflies j
+// and nb - j paired so that each bin fills its own slot and its mirror's.
+// All reads precede all writes.
+template <class P, int T, class TC>
+__device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
+  constexpr int R = P::rad[0], N = P::N, nb = N / R, nu = nb / 2 + 1, hN = N / 2;
+  constexpr int MU = (nu + T - 1) / T;
+  cplx<TC> v1[MU][R], v2[MU][R];
+#pragma unroll
+  for (int i = 0; i < MU; ++i) {
+    const int u = lane + i * T;
+    if (nu % T != 0 && u >= nu) continue;
+    const int kind = unit_kind(u, nb), j1 = u, j2 = nb - u;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      v1[i][q] = {(TC)0, (TC)0};
+      v2[i][q] = {(TC)0, (TC)0};
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int k = j1 + q * nb;
+      if (k <= hN) {
+        const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+        v1[i][q] = conj_z_direct(A, B);
+        const cplx<TC> m = conj_z_mirror(A, B);
+        if (kind == 0) {
+          if (q != 0) v1[i][(R - q) % R] = m;
+        } else if (kind == 1) {
+          if (R - 1 - q != q) v1[i][R - 1 - q] = m;
+        } else {
+          v2[i][R - 1 - q] = m;
+        }
+      }
+    }
+    if (kind == 2) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int k = j2 + q * nb;
+        if (k <= hN) {
+          const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+          v2[i][q] = conj_z_direct(A, B);
+          v1[i][R - 1 - q] = conj_z_mirror(A, B);
+        }
+      }
+    }
+  }
+  tsync<T>();
+#pragma unroll
+  for (int i = 0; i < MU; ++i) {
+    const int u = lane + i * T;
+    if (nu % T != 0 && u >= nu) continue;
+    const int j1 = u, j2 = nb - u;
+    if (unit_kind(u, nb) == 2) {
+      dft<R>(v2[i]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[lds_ix(j2 * R + q)] = v2[i][q];
+    }
+    dft<R>(v1[i]);
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[lds_ix(j1 * R + q)] = v1[i][q];
+  }
+  tsync<T>();
+}
+
+// Last pass (jm = j): time steps t < Nt of both series, scaled by 1/N and
+// rounded to the IFFT and unpad formats, replace the transform in its slab
+// (series s as the real part, s + 1 as the imaginary part of slot t).  All
+// reads precede all writes.
+template <class P, int T, bool HALF, class TC>
+__device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, const cplx<TC>* __restrict__ tw,
+                                           int r_ifft, int r_unpad) {
+  constexpr int S = P::nst - 1, R = P::rad[S], N = P::N, nb = N / R, MB = (nb + T - 1) / T;
+  const cplx<TC>* tws = tw + P::toff(S);
+  const TC inv_n = (TC)(1.0 / (double)N);
+  cplx<TC> v[MB][R];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int j = lane + i * T;
+    if ((nb % T != 0 && j >= nb) || j >= Nt) continue;
+    v[i][0] = lds[lds_ix(j)];
+#pragma unroll
+    for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(j + q * nb)], tws[j * R + q]);
+  }
+  tsync<T>();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int j = lane + i * T;
+    if ((nb % T != 0 && j >= nb) || j >= Nt) continue;
+    dft<R>(v[i]);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int t = j + q * nb;
+      if (t < Nt) {  // W_t = N conj(y_t), y = a + i b
+        const TC ra = round_as<HALF>(v[i][q].x * inv_n, r_ifft), rb = round_as<HALF>(-v[i][q].y * inv_n, r_ifft);
+        lds[lds_ix(t)] = {(TC)round_as<HALF>((double)ra, r_unpad), (TC)round_as<HALF>((double)rb, r_unpad)};
+      }
+    }
+  }
+}
+
+template <class P, class TI, class TC, bool HALF, int T, int C>
+__global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, const cplx<TC>* __restrict__ tw,
+                                                                int64_t ntile) {
+  constexpr int N = P::N, hN = N / 2, WG = C / 2 * T, SL = slab_size<N>(), ROWS = WG / C;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<TC>* slabs = reinterpret_cast<cplx<TC>*>(smem_raw);
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t b = wg / ntile, s0 = (wg - b * ntile) * C;
+  const int tid = threadIdx.x, Nt = a.Nt;
+
+  // tile load of bins k <= N/2, rounded to the IFFT format; the imaginary
+  // parts of bins 0 and N/2 are dropped, as a real inverse transform does
+  {
+    const int c = tid % C;
+    const bool live = s0 + c < a.S;
+    const cplx<TI>* in = reinterpret_cast<const cplx<TI>*>(a.in) + b * a.in_rhs_stride + (live ? s0 + c : 0);
+    cplx<TC>* slab = slabs + (c / 2) * SL;
+    const int off = (c & 1) ? hN + 1 : 0;
+    constexpr int U = 4;
+    for (int k0 = tid / C; k0 <= hN; k0 += U * ROWS) {
+      cplx<TI> v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * ROWS;
+        v[u] = (live && k <= hN) ? in[(int64_t)k * a.in_k_stride] : cplx<TI>{(TI)0, (TI)0};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * ROWS;
+        if (k > hN) continue;
+        cplx<TC> z = round_as<HALF>(cplx<TC>{(TC)v[u].x, (TC)v[u].y}, a.r_ifft);
+        if (k == 0 || k == hN) z.y = (TC)0;
+        slab[lds_ix(off + k)] = z;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int slot = tid / T, lane = tid % T;
+    cplx<TC>* lds = slabs + slot * SL;
+    irfft_first<P, T>(lds, lane);
+    mid_passes<P, 1, T>(lds, lane, tw);
+    irfft_last<P, T, HALF>(lds, Nt, lane, tw, a.r_ifft, a.r_unpad);
+  }
+  __syncthreads();
+  // tile store: rows t < Nt of column c
+  {
+    const int c = tid % C;
+    const int64_t s = s0 + c;
+    if (s >= a.S) return;
+    const TC* src = reinterpret_cast<const TC*>(slabs + (c / 2) * SL) + (c & 1);
+    double* y = (a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride) + s;
+    for (int t = tid / C; t < Nt; t += ROWS) y[(int64_t)t * a.y_row_stride] = (double)src[2 * lds_ix(t)];
+  }
+}
+
+// ---- the plans and workgroup shapes compiled for this length -------------------
+
+#if FTM_FIXED_N == 2000
+using PlanF = CPlan<16, 5, 5, 5>;
+using PlanI = CPlan<5, 5, 5, 16>;
+#elif FTM_FIXED_N == 1024
+using PlanF = CPlan<16, 8, 8>;
+using PlanI = CPlan<8, 8, 16>;
+#elif FTM_FIXED_N == 512
+using PlanF = CPlan<8, 8, 8>;
+using PlanI = CPlan<8, 8, 8>;
+#elif FTM_FIXED_N == 400
+using PlanF = CPlan<16, 5, 5>;
+using PlanI = CPlan<5, 5, 16>;
+#elif FTM_FIXED_N == 256
+using PlanF = CPlan<16, 16>;
+using PlanI = CPlan<16, 16>;
+#elif FTM_FIXED_N == 128
+using PlanF = CPlan<16, 8>;
+using PlanI = CPlan<8, 16>;
+#else
+#error "no fixed plan for this FTM_FIXED_N"
+#endif
+static_assert(PlanF::N == FTM_FIXED_N && PlanI::N == FTM_FIXED_N, "plan length");
+
+// Threads per transform T (a power of two) and columns per tile C.  T gives
+// each thread 128 bytes of its transform's slab (8 float64 or 16 float32
+// points).  C makes a row segment of the float64 input 128 bytes for float32
+// transforms (C = 16) and 64 bytes for float64 ones (C = 8, whose slabs are
+// twice as large), within the 1024 threads and the LDS of one workgroup.
+// Shape 2 halves C (more, smaller workgroups).
+constexpr int pow2_ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+template <class TC>
+constexpr int threads_per_transform() {
+  const int t = pow2_ceil(FTM_FIXED_N * (int)sizeof(cplx<TC>) / 128);
+  return t < 16 ? 16 : (t > 256 ? 256 : t);
+}
+template <class TC>
+constexpr int tile_columns(int shape) {
+  int c = sizeof(TC) == 8 ? 8 : 16;
+  while (c / 2 * threads_per_transform<TC>() > 1024) c /= 2;
+  return shape == 2 ? c / 2 : c;
+}
+
+template <class P>
+bool same_plan(const FftPlan& plan) {
+  if (plan.N != P::N || plan.nst != P::nst) return false;
+  for (int s = 0; s < P::nst; ++s)
+    if (plan.rad[s] != P::rad[s] || plan.toff[s] != P::toff(s)) return false;
+  return true;
+}
+
+bool is_half(int dt) { return dt == DT_F16 || dt == DT_BF16; }
+
+template <class TC, class TO, int SH>
+hipError_t rfft_go(const RfftArgs& a, const void* tw, hipStream_t st) {
+  constexpr int T = threads_per_transform<TC>(), C = tile_columns<TC>(SH), WG = C / 2 * T;
+  const int64_t ntile = (a.S + C - 1) / C;
+  const int64_t nwg = ntile * a.nrhs;
+  if (nwg <= 0) return hipSuccess;
+  if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
+  const size_t lds = (size_t)(C / 2) * slab_size<PlanF::N>() * sizeof(cplx<TC>);
+  const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
+  if (is_half(a.r_pad) || is_half(a.r_fft) || is_half(a.r_next))
+    hipLaunchKernelGGL((rfft_fixed_kernel<PlanF, TC, TO, true, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a, t,
+                       ntile);
+  else
+    hipLaunchKernelGGL((rfft_fixed_kernel<PlanF, TC, TO, false, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
+                       t, ntile);
+  return hipGetLastError();
+}
+
+template <class TI, class TC, int SH>
+hipError_t irfft_go(const IrfftArgs& a, const void* tw, hipStream_t st) {
+  constexpr int T = threads_per_transform<TC>(), C = tile_columns<TC>(SH), WG = C / 2 * T;
+  const int64_t ntile = (a.S + C - 1) / C;
+  const int64_t nwg = ntile * a.nrhs;
+  if (nwg <= 0) return hipSuccess;
+  if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
+  const size_t lds = (size_t)(C / 2) * slab_size<PlanI::N>() * sizeof(cplx<TC>);
+  const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
+  if (is_half(a.r_ifft) || is_half(a.r_unpad))
+    hipLaunchKernelGGL((irfft_fixed_kernel<PlanI, TI, TC, true, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
+                       t, ntile);
+  else
+    hipLaunchKernelGGL((irfft_fixed_kernel<PlanI, TI, TC, false, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
+                       t, ntile);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define FTM_CAT2(a, b) a##b
+#define FTM_CAT(a, b) FTM_CAT2(a, b)
+
+// Forward transform with the plan compiled here; false (nothing launched) when
+// the operator's plan differs.  shape: 0 or 1 the default tile, 2 the smaller.
+bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
+                                                const void* tw, int shape, hipStream_t st, hipError_t* err) {
+  if (!same_plan<PlanF>(plan)) return false;
+  const bool alt = shape == 2;
+  if (tc64 && out64) *err = alt ? rfft_go<double, double, 2>(a, tw, st) : rfft_go<double, double, 1>(a, tw, st);
+  else if (tc64) *err = alt ? rfft_go<double, float, 2>(a, tw, st) : rfft_go<double, float, 1>(a, tw, st);
+  else *err = alt ? rfft_go<float, float, 2>(a, tw, st) : rfft_go<float, float, 1>(a, tw, st);
+  return true;
+}
+
+bool FTM_CAT(launch_irfft_fixed_, FTM_FIXED_N)(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan,
+                                                 const void* tw, int shape, hipStream_t st, hipError_t* err) {
+  if (!same_plan<PlanI>(plan)) return false;
+  const bool alt = shape == 2;
+  if (tc64 && in64) *err = alt ? irfft_go<double, double, 2>(a, tw, st) : irfft_go<double, double, 1>(a, tw, st);
+  else if (tc64) *err = alt ? irfft_go<float, double, 2>(a, tw, st) : irfft_go<float, double, 1>(a, tw, st);
+  else *err = alt ? irfft_go<float, float, 2>(a, tw, st) : irfft_go<float, float, 1>(a, tw, st);
+  return true;
+}
+
+}  // namespace ftm

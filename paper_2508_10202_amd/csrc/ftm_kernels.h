@@ -8,17 +8,19 @@
 namespace ftm {
 
 constexpr int MAX_STAGES = 16;
-// Largest number of complex points one FFT workgroup holds in LDS: P series
-// of length N with P * N <= FFT_POINTS (64 KiB of float64 complex), and the
-// workgroup size of the FFT kernels.
+// Longest transform (complex points): L = 2 Nt, or the next 7-smooth even
+// length, must not exceed it.
 #ifndef FTM_FFT_POINTS
 #define FTM_FFT_POINTS 4096
 #endif
-#ifndef FTM_FFT_THREADS
-#define FTM_FFT_THREADS 512  // kept for reference; the launchers use FFT_TH
-#endif
 constexpr int FFT_POINTS = FTM_FFT_POINTS;
-constexpr int FFT_THREADS = FTM_FFT_THREADS;
+// FFT kernel choices (for the autotuner): 0 the default (the fixed-plan
+// kernels where the length has them, shape 1), 1 and 2 the fixed-plan kernels'
+// two workgroup shapes, 3 the runtime-plan kernels.
+constexpr int FFT_SHAPES = 4;
+constexpr int FFT_SHAPE_GENERIC = 3;
+// Whether length N has fixed-plan kernels.
+bool fft_has_fixed(int N);
 
 // Unsigned 32-bit division by an invariant divisor d via multiply-high
 // (Granlund and Montgomery, PLDI 1994, Fig. 4.1): with l = ceil(log2 d) and
@@ -42,10 +44,10 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, FastDiv f) {
 }
 
 // Mixed-radix plan of a length-N complex FFT: N = rad[0] * rad[1] * ...
-// div_ns[s] divides by Ns = rad[0] * .. * rad[s-1].  Pass s reads its
-// twiddles exp(-2 pi i q jm / (Ns rad[s])) (jm < Ns, q < rad[s]) from the
-// twiddle table at toff[s] + jm * rad[s] + q; twiddle_entries() is the table
-// length.
+// (at least two passes; a radix of 1 is a copy).  div_ns[s] divides by
+// Ns = rad[0] * .. * rad[s-1].  Pass s reads its twiddles
+// exp(-2 pi i q jm / (Ns rad[s])) (jm < Ns, q < rad[s]) from the twiddle
+// table at toff[s] + jm * rad[s] + q; twiddle_entries() is the table length.
 struct FftPlan {
   int N;
   int nst;
@@ -105,10 +107,19 @@ struct GemvArgs {
 // Number of tile-shape variants of the matrix-vector kernels.
 constexpr int GEMV_VARIANTS = 4;
 
-hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
-                       const void* tw, hipStream_t st);
-hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan,
-                        const void* tw, hipStream_t st);
+// The plans (and twiddle tables, in the transform's compute type) a transform
+// can run: `fixed` for the fixed-plan kernels (descending radices for the
+// forward transform, ascending for the inverse one, so that their paired
+// passes take the smallest radix) and `generic` for the runtime-plan kernels.
+struct FftPlans {
+  const FftPlan* fixed;
+  const void* fixed_tw;
+  const FftPlan* generic;
+  const void* generic_tw;
+};
+// shape: the kernel choice (0 = default; FFT_SHAPES above).
+hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlans& pl, int shape, hipStream_t st);
+hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlans& pl, int shape, hipStream_t st);
 hipError_t launch_gemv_fwd(int fdt, bool acc64, bool in64, bool out64, const GemvArgs& a,
                            hipStream_t st);
 hipError_t launch_gemv_adj(int fdt, bool acc64, bool in64, bool out64, const GemvArgs& a,

@@ -44,6 +44,8 @@ struct MatvecIO {
 struct Exec {
   ftm_precision p{};
   int gemv_variant = 0;
+  int fft_shape_in = 0, fft_shape_out = 0;  // kernels of the two transforms (0 = default)
+  int gemm_tile = 0;                         // right-hand sides per GEMM tile (0 = default)
   bool use_gemm = false;
   bool profile = false;  // record HIP events around the kernels
 };
@@ -55,8 +57,20 @@ struct ftm_operator_s {
   int ldm = 0, ldd = 0;  // padded column counts of spectra and workspaces
   int device = 0;
   int64_t max_rhs = 1;
-  ftm::FftPlan plan{}, plan32{};  // length-L plans of the float64 and float32 transforms
-  ftm_rt::DevBuf tw64, tw32;     // their per-pass twiddle tables
+  // length-L plans: plan_f / plan_i for the fixed-plan forward (descending
+  // radices) and inverse (ascending) kernels, and in float32 for the
+  // runtime-plan kernels too; plan_g64 (radices up to 8) for the float64
+  // runtime-plan kernels.  Their per-pass twiddle tables in the compute types.
+  ftm::FftPlan plan_f{}, plan_i{}, plan_g64{};
+  ftm_rt::DevBuf tw64f, tw64i, tw32f, tw32i, twg64;
+  // the plans and tables of the input (forward) and output (inverse)
+  // transform for float64 (f64 = true) or float32 compute
+  ftm::FftPlans fft_in(bool f64) const {
+    return f64 ? ftm::FftPlans{&plan_f, tw64f.p, &plan_g64, twg64.p} : ftm::FftPlans{&plan_f, tw32f.p, &plan_f, tw32f.p};
+  }
+  ftm::FftPlans fft_out(bool f64) const {
+    return f64 ? ftm::FftPlans{&plan_i, tw64i.p, &plan_g64, twg64.p} : ftm::FftPlans{&plan_i, tw32i.p, &plan_f, tw32f.p};
+  }
   ftm_rt::DevBuf spec[4];     // Fhat[K][Nd][ldm] per storage format
   ftm_rt::DevBuf mhat, dhat;  // the operator's own workspace, sized for max_rhs
 
@@ -64,8 +78,10 @@ struct ftm_operator_s {
   mutable std::mutex mu;
   ftm_precision fwd{}, adj{};
   int rhs_mode = FTM_RHS_AUTO;
-  int64_t gemm_min_rhs = 2;
-  int variant[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // [direction][storage format] tile variant
+  int64_t gemm_min_rhs[2][4] = {{2, 2, 2, 2}, {2, 2, 2, 2}};  // [direction][storage format] crossover
+  int variant[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};          // [direction][storage format] tile variant
+  int gemm_tile[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};        // [direction][storage format] GEMM tile
+  int fft_shape[2][2][2] = {};  // [direction][input / output transform][float64 compute] transform kernel
   double tuned_ms[2] = {0.0, 0.0};
   bool profiling = false;
   struct Rec {
@@ -76,7 +92,7 @@ struct ftm_operator_s {
   std::vector<hipEvent_t> event_pool;
 
   size_t bytes() const {
-    size_t b = tw64.n + tw32.n + mhat.n + dhat.n;
+    size_t b = tw64f.n + tw64i.n + tw32f.n + tw32i.n + twg64.n + mhat.n + dhat.n;
     for (const auto& s : spec) b += s.n;
     return b;
   }

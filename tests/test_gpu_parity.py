@@ -77,6 +77,14 @@ RAGGED = [
     Shape(23, 5, 40, decay=10.0),     # 46 -> 48
     Shape(97, 4, 33, decay=40.0),     # 194 -> 196 = 4*7*7
     Shape(2047, 2, 5, decay=500.0),   # 4094 -> 4096
+    # lengths with fixed-plan transform kernels: partial column tiles, a single
+    # column, odd column counts, and Nt below L/2 (L padded to the fixed length)
+    Shape(64, 3, 33, decay=None),     # L = 128
+    Shape(127, 5, 17, decay=50.0),    # 254 -> 256
+    Shape(199, 9, 45, decay=60.0),    # 398 -> 400
+    Shape(512, 2, 1, decay=200.0),    # L = 1024, one parameter column
+    Shape(256, 17, 23, decay=100.0),  # L = 512
+    Shape(997, 3, 37, decay=300.0),   # 1994 -> 2000
 ]
 
 
@@ -452,30 +460,39 @@ def test_graph_replays_match_eager(gpu):
 
 
 def test_autotune_keeps_results_and_caches(gpu, tmp_path):
+    """The autotuner picks among kernels that all compute the same product:
+    every product tile variant and every transform kernel (fixed-plan large
+    and small tile, runtime-plan) against the oracle, in float64 and float32."""
     import torch
     from paper_2508_10202_amd import Operator
-    s = Shape(100, 37, 1000)
-    F, m, d = make_F(s, 111), make_m(s, 112)[0], make_d(s, 113)[0]
-    op = Operator(torch.from_numpy(F).cuda(), spectra=("s",))
-    cache = str(tmp_path / "tune.json")
-    rec = op.autotune(reps=3, cache=cache)
-    assert not rec["cached"] and 0 <= rec["fwd_variant"] < 4 and 0 <= rec["adj_variant"] < 4
-    assert rec["fwd_ms"] > 0 and rec["adj_ms"] > 0
-    assert op.autotune(cache=cache)["cached"]
-    mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
-    ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
-    for prec, tol in (("ddddd", FP64_TOL), ("sssss", mp_bounds("sssss", s.L, s.Nm)[1])):
-        op.set_precision(fwd=prec, adj=prec)
-        outs = []
-        for v in range(4):                      # every variant computes the same product
-            op.set_tuning(v, v)
-            yd, ym = op.matvec(mt).cpu().numpy(), op.rmatvec(dt).cpu().numpy()
-            assert _rel(yd, ref_d) <= tol and _rel(ym, ref_m) <= tol, (prec, v)
-            outs.append((yd, ym))
-        if prec == "ddddd":                     # same summation order within each output
-            for yd, ym in outs[1:]:
-                assert _rel(yd, outs[0][0]) <= 1e-14 and _rel(ym, outs[0][1]) <= 1e-14
-    from paper_2508_10202_amd import FtmError
-    with pytest.raises(FtmError):
-        op.set_tuning(4, 0)
-    op.close()
+    from paper_2508_10202_amd._lib import FFT_GENERIC
+    for s in (Shape(200, 37, 1000), Shape(90, 11, 333, decay=30.0)):   # L = 400 (fixed plan), 180 (runtime plan)
+        _say("case autotune", s)
+        F, m, d = make_F(s, 111), make_m(s, 112)[0], make_d(s, 113)[0]
+        op = Operator(torch.from_numpy(F).cuda(), spectra=("s",))
+        cache = str(tmp_path / f"tune{s.Nt}.json")
+        rec = op.autotune(reps=3, cache=cache)
+        assert not rec["cached"] and all(0 <= v < 4 for v in rec["gemv_variant"])
+        assert all(0 <= v <= FFT_GENERIC for r in rec["fft_shape"] for v in r)
+        assert all(t > 0 for t in rec["ms"])
+        assert op.autotune(cache=cache)["cached"]
+        mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
+        ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
+        for prec, tol in (("ddddd", FP64_TOL), ("sssss", mp_bounds("sssss", s.L, s.Nm)[1])):
+            op.set_precision(fwd=prec, adj=prec)
+            outs = []
+            for v in range(4):                      # every product variant computes the same product
+                for sh in range(FFT_GENERIC + 1):   # and every transform kernel
+                    op.set_tuning(gemv_variant=(v, v), fft_shape=((sh, sh), (sh, sh)))
+                    yd, ym = op.matvec(mt).cpu().numpy(), op.rmatvec(dt).cpu().numpy()
+                    assert _rel(yd, ref_d) <= tol and _rel(ym, ref_m) <= tol, (prec, v, sh)
+                    outs.append((yd, ym))
+            if prec == "ddddd":
+                for yd, ym in outs[1:]:
+                    assert _rel(yd, outs[0][0]) <= 1e-14 and _rel(ym, outs[0][1]) <= 1e-14
+        from paper_2508_10202_amd import FtmError
+        with pytest.raises(FtmError):
+            op.set_tuning(gemv_variant=(4, 0))
+        with pytest.raises(FtmError):
+            op.set_tuning(fft_shape=((4, 0), (0, 0)))
+        op.close()
