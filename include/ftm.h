@@ -103,6 +103,22 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
                               int64_t Nm, const ftm_precision* fwd, const ftm_precision* adj,
                               uint32_t spectra, int64_t max_rhs, void* stream);
 
+/* ftm_setup_operator for F in another memory layout: element (t, r, c) of
+ * the first block column is F[t * stride_t + r * stride_r + c * stride_c]
+ * (strides in elements).  Solver-native layouts (Section 2.4: the first block
+ * column comes from Nd adjoint PDE solves, e.g. time series stored contiguously
+ * per sensor and parameter, [Nd][Nm][Nt] or [Nm][Nd][Nt]) are read directly by
+ * the setup transform: no permuted copy of F is made (the permutation kernel
+ * of Section 3.1 is folded into the transform's loads).  The spectrum equals
+ * the one of the same F in the [Nt][Nd][Nm] layout, bitwise.
+ * FTM_ERR_INVALID also when the strides let two elements overlap (in
+ * increasing stride order each stride must be at least the span of the
+ * smaller ones; strides of extent-1 dimensions are ignored). */
+ftm_status ftm_setup_operator_strided(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd, int64_t Nm,
+                                      int64_t stride_t, int64_t stride_r, int64_t stride_c,
+                                      const ftm_precision* fwd, const ftm_precision* adj, uint32_t spectra,
+                                      int64_t max_rhs, void* stream);
+
 /* Change the precision configuration (NULL leaves a direction unchanged).
  * Fails with FTM_ERR_UNSUPPORTED if the needed Fhat copy was not kept. */
 ftm_status ftm_set_precision(ftm_operator op, const ftm_precision* fwd, const ftm_precision* adj);
@@ -141,6 +157,35 @@ ftm_status ftm_workspace_size(ftm_operator op, int32_t adjoint, int64_t nrhs, si
 ftm_status ftm_apply(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* Data-space Hessian actions y = F Gamma F^T x with Gamma = I (the dense
+ * data-space Hessian of the outer-loop problems in Section 3.2 takes
+ * Nd * Nt of them; Section 2.3 applies F^* inside the MAP point): for each of
+ * nrhs data vectors, the adjoint matvec into a float64 parameter-space
+ * intermediate, then the forward matvec, each at its direction's precision
+ * configuration (the many-right-hand-side path of ftm_set_rhs_mode applies to
+ * both).
+ *   x, y       device float64 [nrhs][Nt][Nd]; must not overlap.
+ *   workspace  device memory of at least ftm_hessian_workspace_size(op, nrhs)
+ *              bytes (nrhs * Nt * Nm * 8 for the intermediate, rounded up to
+ *              256, plus the larger of the two directions'
+ *              ftm_workspace_size), 256-byte aligned, not overlapping x or y;
+ *              contents on entry do not matter.  The call allocates nothing.
+ * 1 <= nrhs <= 2^20.  Calls with distinct workspaces may run concurrently on
+ * different streams.  FTM_ERR_INVALID: NULL pointers, nrhs out of range, a
+ * workspace that is too small, misaligned or overlapping. */
+ftm_status ftm_hessian_workspace_size(ftm_operator op, int64_t nrhs, size_t* bytes);
+ftm_status ftm_hessian_apply(ftm_operator op, const double* x, double* y, int64_t nrhs, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* Round n values into storage format dtype exactly as every phase does
+ * (round to nearest, ties to even; values beyond the format's range become
+ * infinities, NaN stays NaN; Section 3.2 casts).  With from_f32 the values are
+ * first rounded to float32 and the float32 path of the kernels is used (as in
+ * phases that compute in float32).
+ *   x, y  device float64 [n] (may be the same array).
+ * FTM_ERR_INVALID: unknown dtype, n < 0, NULL pointers with n > 0. */
+ftm_status ftm_round(int32_t dtype, int32_t from_f32, const double* x, double* y, int64_t n, void* stream);
+
 /* Bytes of the library's static scratch workspace on each GPU (96 MiB: one
  * float64 vector at Nt=1000, Nd=100, Nm=5000 needs 81.8 MB). */
 #define FTM_SCRATCH_BYTES ((size_t)96 << 20)
@@ -162,12 +207,15 @@ ftm_status ftm_apply_scratch(ftm_operator op, int32_t adjoint, const double* x, 
                              void* stream);
 
 /* How phase 3 treats nrhs > 1 right-hand sides:
- *   FTM_RHS_AUTO  (default) matrix-core GEMM when the product's storage is
- *                 FP32/FP16/BF16 with FP32 accumulation and nrhs >= the
- *                 operator's crossover (see ftm_set_gemm_crossover), else one
- *                 matrix-vector product per right-hand side
+ *   FTM_RHS_AUTO  (default) a complex GEMM per frequency on the matrix cores
+ *                 when nrhs >= the crossover (ftm_set_gemm_crossover,
+ *                 ftm_set_tuning), else one matrix-vector product per
+ *                 right-hand side.  The GEMM accumulates in float64 for
+ *                 FP64 products and FP32 ones with accum FTM_F64, in float32
+ *                 otherwise; a vector's result does not depend on the batch
+ *                 around it.
  *   FTM_RHS_GEMV  always one matrix-vector product per right-hand side
- *   FTM_RHS_GEMM  the GEMM whenever the configuration allows it */
+ *   FTM_RHS_GEMM  the GEMM for every nrhs >= 2 */
 typedef enum ftm_rhs_mode { FTM_RHS_AUTO = 0, FTM_RHS_GEMV = 1, FTM_RHS_GEMM = 2 } ftm_rhs_mode;
 ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode);
 
@@ -204,7 +252,10 @@ typedef struct ftm_tuning {
  * points from measurements): for both directions at the operator's current
  * precision configuration, time the matrix-vector tile variants and the
  * transform kernels on one vector (reps timed runs each, scratch inputs) and
- * keep the fastest.  Synchronises the stream.  ftm_get_tuning /
+ * keep the fastest; then set the GEMM crossover to the smallest batch of 2,
+ * 4, .., 32 right-hand sides for which the matrix-core product is no slower
+ * than one matrix-vector product per vector (33 if none; this probe
+ * allocates inputs and workspace for 32 vectors).  Synchronises the stream.  ftm_get_tuning /
  * ftm_set_tuning read and set the choice (for a persistent tuning cache kept
  * by the caller).  Out-of-range values are FTM_ERR_INVALID. */
 ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream);

@@ -5,4 +5,4 @@
 There is no CPU fallback: without the built library every call raises.
 """
 from ._lib import BF16, F16, F32, F64, FtmError  # noqa: F401
-from .api import Operator, Precision, Server, sbgemv  # noqa: F401
+from .api import Operator, Precision, Server, round_values, sbgemv  # noqa: F401

@@ -28,8 +28,9 @@ OP_N, OP_T, OP_C = range(3)
 SCRATCH_BYTES = 96 << 20
 
 # Every symbol include/ftm.h declares.
-EXPORTS = ("ftm_setup_operator", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
+EXPORTS = ("ftm_setup_operator", "ftm_setup_operator_strided", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
            "ftm_workspace_size", "ftm_apply", "ftm_apply_scratch",
+           "ftm_hessian_workspace_size", "ftm_hessian_apply", "ftm_round",
            "ftm_get_spectrum", "ftm_operator_info", "ftm_profile_enable", "ftm_profile_read",
            "ftm_set_rhs_mode", "ftm_set_gemm_crossover", "ftm_autotune", "ftm_get_tuning",
            "ftm_set_tuning", "ftm_graph_create", "ftm_graph_launch", "ftm_graph_destroy",
@@ -80,12 +81,17 @@ def lib() -> ctypes.CDLL:
     prec_p = ctypes.POINTER(FtmPrecision)
     sigs = {
         "ftm_setup_operator": [ctypes.POINTER(vp), vp, i64, i64, i64, prec_p, prec_p, u32, i64, vp],
+        "ftm_setup_operator_strided": [ctypes.POINTER(vp), vp, i64, i64, i64, i64, i64, i64, prec_p, prec_p, u32,
+                                       i64, vp],
         "ftm_set_precision": [vp, prec_p, prec_p],
         "ftm_matvec": [vp, vp, vp, i64, vp],
         "ftm_rmatvec": [vp, vp, vp, i64, vp],
         "ftm_workspace_size": [vp, i32, i64, ctypes.POINTER(ctypes.c_size_t)],
         "ftm_apply": [vp, i32, vp, vp, i64, vp, ctypes.c_size_t, vp],
         "ftm_apply_scratch": [vp, i32, vp, vp, i64, vp],
+        "ftm_hessian_workspace_size": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
+        "ftm_hessian_apply": [vp, vp, vp, i64, vp, ctypes.c_size_t, vp],
+        "ftm_round": [i32, i32, vp, vp, i64, vp],
         "ftm_get_spectrum": [vp, i32, i64, i64, vp, vp],
         "ftm_operator_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                               ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],

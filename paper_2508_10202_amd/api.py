@@ -83,14 +83,17 @@ def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
 class Operator:
     """Block lower-triangular Toeplitz operator held on the GPU as its spectrum.
 
-    ``F`` is the first block column, a float64 CUDA tensor ``[Nt, Nd, Nm]``.
+    ``F`` is the first block column, a float64 CUDA tensor ``[Nt, Nd, Nm]``;
+    any strided view works (e.g. ``G.permute(2, 0, 1)`` of a ``[Nd, Nm, Nt]``
+    array): the setup transform reads the strides directly.
     ``spectra`` lists extra storage formats to keep for later
     :meth:`set_precision` calls (e.g. ``("s", "h")``).
     """
 
     def __init__(self, F: torch.Tensor, fwd=None, adj=None, spectra=(), max_rhs: int = 1,
                  stream=None):
-        F = _dev_f64(F, "F")
+        if not isinstance(F, torch.Tensor) or not F.is_cuda or F.dtype != torch.float64:
+            raise TypeError("F must be a float64 CUDA (HIP) tensor")
         if F.dim() != 3:
             raise ValueError("F must be [Nt, Nd, Nm]")
         self.Nt, self.Nd, self.Nm = (int(x) for x in F.shape)
@@ -104,9 +107,10 @@ class Operator:
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = _stream_ptr(stream)
-            check(L.ftm_setup_operator(ctypes.byref(h), F.data_ptr(), self.Nt, self.Nd, self.Nm,
-                                       ctypes.byref(fwd.c()), ctypes.byref(adj.c()), mask,
-                                       self.max_rhs, st), "ftm_setup_operator")
+            st_t, st_r, st_c = F.stride()
+            check(L.ftm_setup_operator_strided(ctypes.byref(h), F.data_ptr(), self.Nt, self.Nd, self.Nm, st_t, st_r,
+                                               st_c, ctypes.byref(fwd.c()), ctypes.byref(adj.c()), mask,
+                                               self.max_rhs, st), "ftm_setup_operator_strided")
         self._h = h
         self.fwd, self.adj = fwd, adj
         Lc = ctypes.c_int64()
@@ -218,6 +222,42 @@ class Operator:
         with torch.cuda.device(x.device):
             check(lib().ftm_apply_scratch(self.handle, 1 if adjoint else 0, xb.data_ptr(), out.data_ptr(), nrhs,
                                           _stream_ptr(stream)), "ftm_apply_scratch")
+        return out[0] if single and out.dim() == 3 else out
+
+    def hessian_workspace_size(self, nrhs: int = 1) -> int:
+        """Workspace bytes of one :meth:`hessian` call of ``nrhs`` vectors."""
+        n = ctypes.c_size_t()
+        check(lib().ftm_hessian_workspace_size(self.handle, int(nrhs), ctypes.byref(n)),
+              "ftm_hessian_workspace_size")
+        return int(n.value)
+
+    def hessian(self, x: torch.Tensor, workspace: torch.Tensor | None = None, out=None,
+                stream=None) -> torch.Tensor:
+        """Data-space Hessian actions ``F F^T x`` (``ftm_hessian_apply``) for
+        ``x`` of shape ``[Nt, Nd]`` or ``[nrhs, Nt, Nd]``.  ``workspace`` (a
+        contiguous CUDA tensor of at least :meth:`hessian_workspace_size`
+        bytes) is allocated here when not given."""
+        x = _dev_f64(x, "x")
+        single = x.dim() == 2
+        xb = x.unsqueeze(0) if single else x
+        if xb.dim() != 3 or tuple(xb.shape[1:]) != (self.Nt, self.Nd):
+            raise ValueError(f"input must be [nrhs,] {self.Nt} x {self.Nd}, got {tuple(x.shape)}")
+        nrhs = xb.shape[0]
+        if workspace is None:
+            workspace = torch.empty(((self.hessian_workspace_size(nrhs) + 255) // 256 * 32,),
+                                    dtype=torch.float64, device=x.device)
+        if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or not workspace.is_contiguous():
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        if out is None:
+            out = torch.empty_like(xb)
+        else:
+            out = _dev_f64(out, "out")
+            if out.numel() != xb.numel():
+                raise ValueError("out has the wrong size")
+        nbytes = workspace.numel() * workspace.element_size()
+        with torch.cuda.device(x.device):
+            check(lib().ftm_hessian_apply(self.handle, xb.data_ptr(), out.data_ptr(), nrhs, workspace.data_ptr(),
+                                          nbytes, _stream_ptr(stream)), "ftm_hessian_apply")
         return out[0] if single and out.dim() == 3 else out
 
     def spectrum(self, which="d", k0: int = 0, nk: int | None = None, stream=None) -> torch.Tensor:
@@ -493,4 +533,15 @@ def sbgemv(A: torch.Tensor, x: torch.Tensor, m: int | None = None, op: str = "N"
         check(lib().ftm_sbgemv(code, _SB_OPS[op], m, n, ctypes.cast(al, ctypes.c_void_p), A.data_ptr(), lda,
                                n * lda, x.data_ptr(), nx, ctypes.cast(be, ctypes.c_void_p), y.data_ptr(), ny,
                                batch, _stream_ptr(stream)), "ftm_sbgemv")
+    return y
+
+
+def round_values(x: torch.Tensor, fmt: str, from_f32: bool = False, stream=None) -> torch.Tensor:
+    """Round a float64 CUDA tensor into storage format ``fmt`` (one of d/s/h/b)
+    exactly as the kernels do (``ftm_round``); returns float64 values."""
+    x = _dev_f64(x, "x")
+    y = torch.empty_like(x)
+    with torch.cuda.device(x.device):
+        check(lib().ftm_round(_CODE[fmt], 1 if from_f32 else 0, x.data_ptr(), y.data_ptr(), x.numel(),
+                              _stream_ptr(stream)), "ftm_round")
     return y

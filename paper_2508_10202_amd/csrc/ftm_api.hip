@@ -60,7 +60,8 @@ ftm_rt::Exec ftm_operator_s::exec(bool adjoint, int64_t nrhs, bool allow_profile
   e.fft_shape_out = fft_shape[adjoint ? 1 : 0][1][e.p.ifft == ftm::DT_F64 ? 1 : 0];
   e.gemm_tile = gemm_tile[adjoint ? 1 : 0][e.p.gemv];
   // many right-hand sides: one pass of the spectrum through the matrix cores
-  const bool gemm_ok = e.p.gemv != ftm::DT_F64 && e.p.accum != ftm::DT_F64 && nrhs >= 2;
+  // (float64 accumulation on the float64 ones, float32 on the others)
+  const bool gemm_ok = nrhs >= 2;
   e.use_gemm = gemm_ok && (rhs_mode == FTM_RHS_GEMM ||
                            (rhs_mode == FTM_RHS_AUTO && nrhs >= gemm_min_rhs[adjoint ? 1 : 0][e.p.gemv]));
   e.profile = allow_profile && profiling;
@@ -296,6 +297,8 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ra.pad_to = ldx;
   ra.x_rhs_stride = op->Nt * Sx;
   ra.x_row_stride = Sx;
+  ra.x_sr = 0;
+  ra.x_sc = 1;
   ra.S = Sx;
   ra.Nt = (int)op->Nt;
   ra.nrhs = (int)nrhs;
@@ -328,10 +331,12 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ga.r_gemv = p.gemv;
   ga.r_next = p.ifft;
   ga.variant = ex.gemv_variant;
+  ga.rhs_tile = ex.gemm_tile;
   const bool acc64 = p.accum == DT_F64;
   prof.mark(1);
   if (ex.use_gemm) {
-    if (adjoint) FTM_HIP(launch_gemm_adj(p.gemv, ga, st));
+    if (acc64) FTM_HIP(launch_gemm_a64(adjoint, p.gemv, x_hat64, y_hat64, ga, st));
+    else if (adjoint) FTM_HIP(launch_gemm_adj(p.gemv, ga, st));
     else FTM_HIP(launch_gemm_fwd(p.gemv, ga, st));
   } else if (adjoint) {
     FTM_HIP(launch_gemv_adj(p.gemv, acc64, x_hat64, y_hat64, ga, st));
@@ -404,12 +409,34 @@ const char* ftm_last_error(void) { return ftm_rt::g_last_error.c_str(); }
 ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd, int64_t Nm,
                               const ftm_precision* fwd, const ftm_precision* adj, uint32_t spectra,
                               int64_t max_rhs, void* stream) {
+  return ftm_setup_operator_strided(out, F, Nt, Nd, Nm, Nd * Nm, Nm, 1, fwd, adj, spectra, max_rhs, stream);
+}
+
+ftm_status ftm_setup_operator_strided(ftm_operator* out, const double* F, int64_t Nt, int64_t Nd, int64_t Nm,
+                                      int64_t stride_t, int64_t stride_r, int64_t stride_c,
+                                      const ftm_precision* fwd, const ftm_precision* adj, uint32_t spectra,
+                                      int64_t max_rhs, void* stream) {
   try {
     if (!out) return fail(FTM_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!F) return fail(FTM_ERR_INVALID, "F is NULL");
     if (Nt < 1 || Nd < 1 || Nm < 1 || max_rhs < 1)
       return fail(FTM_ERR_INVALID, "Nt, Nd, Nm and max_rhs must be >= 1");
+    {
+      // the strides must address every (t, r, c) at a distinct element: in
+      // increasing stride order, each stride at least the span of the smaller ones
+      int64_t st[3] = {stride_t, stride_r, stride_c}, ex[3] = {Nt, Nd, Nm};
+      for (int i = 0; i < 3; ++i)
+        if (ex[i] > 1 && st[i] < 1) return fail(FTM_ERR_INVALID, "strides of dimensions longer than 1 must be >= 1");
+      int ord[3] = {0, 1, 2};
+      std::sort(ord, ord + 3, [&](int a, int b) { return st[a] < st[b]; });
+      int64_t span = 1;
+      for (int i = 0; i < 3; ++i) {
+        if (ex[ord[i]] == 1) continue;
+        if (st[ord[i]] < span) return fail(FTM_ERR_INVALID, "strides make elements of F overlap");
+        span = st[ord[i]] * ex[ord[i]];
+      }
+    }
     // pad length: 2 Nt when it factors into 2, 3, 5 and 7 (the paper's
     // choice), else the next even length that does -- circular and linear
     // convolution agree on the first Nt outputs for any L >= 2 Nt - 1
@@ -466,7 +493,9 @@ ftm_status ftm_setup_operator(ftm_operator* out, const double* F, int64_t Nt, in
     RfftArgs ra{};
     ra.x = F;
     ra.x_rhs_stride = 0;
-    ra.x_row_stride = Nd * Nm;
+    ra.x_row_stride = stride_t;
+    ra.x_sr = stride_r;
+    ra.x_sc = stride_c;
     ra.S = Nd * Nm;
     ra.Nt = (int)Nt;
     ra.nrhs = 1;
@@ -566,6 +595,59 @@ ftm_status ftm_workspace_size(ftm_operator op, int32_t adjoint, int64_t nrhs, si
   return FTM_OK;
 }
 
+// Workspace of one data-space Hessian action on nrhs vectors: the float64
+// parameter-space intermediate F^T x ([nrhs][Nt][Nm]), then room for the
+// larger of the two directions' transform workspaces.
+static size_t hessian_bytes(const ftm_operator_s* op, int64_t nrhs, const ftm_rt::Exec& ef,
+                            const ftm_rt::Exec& ea) {
+  const size_t mid = ftm_operator_s::round256((size_t)nrhs * op->Nt * op->Nm * 8);
+  const size_t wf = op->workspace_bytes(nrhs, false, ef.p), wa = op->workspace_bytes(nrhs, true, ea.p);
+  return mid + (wf > wa ? wf : wa);
+}
+
+ftm_status ftm_hessian_workspace_size(ftm_operator op, int64_t nrhs, size_t* bytes) {
+  if (!op || !bytes) return fail(FTM_ERR_INVALID, "operator or bytes is NULL");
+  if (nrhs < 1 || nrhs > kMaxCallRhs) return fail(FTM_ERR_INVALID, "nrhs must be in [1, 2^20]");
+  *bytes = hessian_bytes(op, nrhs, op->exec(false, nrhs, false), op->exec(true, nrhs, false));
+  return FTM_OK;
+}
+
+ftm_status ftm_hessian_apply(ftm_operator op, const double* x, double* y, int64_t nrhs, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  try {
+    if (!op) return fail(FTM_ERR_INVALID, "operator is NULL");
+    if (!x || !y || !workspace) return fail(FTM_ERR_INVALID, "input, output or workspace is NULL");
+    if (nrhs < 1 || nrhs > kMaxCallRhs) return fail(FTM_ERR_INVALID, "nrhs must be in [1, 2^20]");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(FTM_ERR_INVALID, "workspace must be 256-byte aligned");
+    const size_t nb = (size_t)nrhs * op->Nt * op->Nd * 8;
+    if (overlaps(x, nb, y, nb)) return fail(FTM_ERR_INVALID, "input and output overlap");
+    // both directions' configurations are copied now: the pair runs as one call
+    const ftm_rt::Exec ea = op->exec(true, nrhs, true), ef = op->exec(false, nrhs, true);
+    const size_t need = hessian_bytes(op, nrhs, ef, ea);
+    if (workspace_bytes < need)
+      return fail(FTM_ERR_INVALID, "workspace of " + std::to_string(workspace_bytes) + " bytes, the call needs " +
+                                       std::to_string(need));
+    if (overlaps(workspace, need, x, nb) || overlaps(workspace, need, y, nb))
+      return fail(FTM_ERR_INVALID, "workspace overlaps the input or the output");
+    DeviceGuard g(op->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* base = reinterpret_cast<char*>(workspace);
+    double* mid = reinterpret_cast<double*>(base);
+    void* tws = base + ftm_operator_s::round256((size_t)nrhs * op->Nt * op->Nm * 8);
+    ftm_rt::MatvecIO io;
+    io.x = x;
+    io.y = mid;
+    ftm_status s = ftm_rt::run_matvec(op, true, ea, io, nrhs, ftm_rt::carve_workspace(op, tws, nrhs, true, ea.p), st);
+    if (s != FTM_OK) return s;
+    io.x = mid;
+    io.y = y;
+    return ftm_rt::run_matvec(op, false, ef, io, nrhs, ftm_rt::carve_workspace(op, tws, nrhs, false, ef.p), st);
+  } catch (...) {
+    return fail(FTM_ERR_INVALID, "unexpected exception in ftm_hessian_apply");
+  }
+}
+
 ftm_status ftm_apply(ftm_operator op, int32_t adjoint, const double* x, double* y, int64_t nrhs, void* workspace,
                      size_t workspace_bytes, void* stream) {
   try {
@@ -651,6 +733,15 @@ ftm_status ftm_matvec(ftm_operator op, const double* m, double* d, int64_t nrhs,
 
 ftm_status ftm_rmatvec(ftm_operator op, const double* d, double* m, int64_t nrhs, void* stream) {
   return matvec_common(op, true, d, m, nrhs, stream);
+}
+
+ftm_status ftm_round(int32_t dtype, int32_t from_f32, const double* x, double* y, int64_t n, void* stream) {
+  if (!valid_dtype(dtype)) return fail(FTM_ERR_INVALID, "dtype must be an ftm_dtype");
+  if (n < 0) return fail(FTM_ERR_INVALID, "n must be >= 0");
+  if (n == 0) return FTM_OK;
+  if (!x || !y) return fail(FTM_ERR_INVALID, "x or y is NULL");
+  FTM_HIP(launch_round_values(dtype, from_f32 != 0, x, y, n, reinterpret_cast<hipStream_t>(stream)));
+  return FTM_OK;
 }
 
 ftm_status ftm_get_spectrum(ftm_operator op, int32_t which, int64_t k0, int64_t nk, double* out, void* stream) {
@@ -808,6 +899,66 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
     best[dir] = b;
     best_t[dir] = bt;
   }
+  // GEMV <-> GEMM crossover per direction: the smallest batch of 2 .. 32
+  // right-hand sides for which the matrix-core product (at its default tile)
+  // is no slower than one matrix-vector product per vector (33: never up to 32)
+  constexpr int kMaxProbe = 32;
+  int64_t cross[2] = {2, 2};
+  {
+    DevBuf xb, yb, wb;
+    const size_t nbig = (size_t)kMaxProbe * nx * 8;
+    size_t wbytes = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+      const size_t w = op->workspace_bytes(kMaxProbe, dir == 1, best[dir].p);
+      wbytes = w > wbytes ? w : wbytes;
+    }
+    if ((s = dev_alloc(&xb, nbig)) != FTM_OK) return done(s);
+    if ((s = dev_alloc(&yb, nbig)) != FTM_OK || (s = dev_alloc(&wb, wbytes)) != FTM_OK) {
+      dev_free(&xb);
+      dev_free(&yb);
+      return done(s);
+    }
+    auto release_probe = [&](ftm_status r) {
+      (void)hipStreamSynchronize(st);
+      dev_free(&xb);
+      dev_free(&yb);
+      dev_free(&wb);
+      return done(r);
+    };
+    if (hipMemsetAsync(xb.p, 0x3f, xb.n, st) != hipSuccess) return release_probe(fail(FTM_ERR_HIP, "hipMemsetAsync"));
+    ftm_rt::MatvecIO pio;
+    pio.x = reinterpret_cast<const double*>(xb.p);
+    pio.y = reinterpret_cast<double*>(yb.p);
+    for (int dir = 0; dir < 2; ++dir) {
+      cross[dir] = kMaxProbe + 1;
+      for (int n = 2; n <= kMaxProbe; n *= 2) {
+        double t_gemm = 0.0, t_gemv = 0.0;
+        for (int g = 0; g < 2; ++g) {
+          ftm_rt::Exec ex = best[dir];
+          ex.use_gemm = g == 0;
+          ex.gemm_tile = 0;
+          const ftm_rt::Workspace pws = ftm_rt::carve_workspace(op, wb.p, n, dir == 1, ex.p);
+          ftm_status r = ftm_rt::run_matvec(op, dir == 1, ex, pio, n, pws, st);
+          if (r != FTM_OK) return release_probe(r);
+          (void)hipEventRecord(e0, st);
+          for (int i = 0; i < reps; ++i) ftm_rt::run_matvec(op, dir == 1, ex, pio, n, pws, st);
+          (void)hipEventRecord(e1, st);
+          if (hipEventSynchronize(e1) != hipSuccess) return release_probe(fail(FTM_ERR_HIP, "hipEventSynchronize"));
+          float t = 0.f;
+          (void)hipEventElapsedTime(&t, e0, e1);
+          (g == 0 ? t_gemm : t_gemv) = t;
+        }
+        if (t_gemm <= t_gemv) {
+          cross[dir] = n;
+          break;
+        }
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    dev_free(&xb);
+    dev_free(&yb);
+    dev_free(&wb);
+  }
   {
     // keep the winners for the formats they were timed with
     std::lock_guard<std::mutex> lk(op->mu);
@@ -816,6 +967,7 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
       op->variant[dir][p.gemv] = best[dir].gemv_variant;
       op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0] = best[dir].fft_shape_in;
       op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0] = best[dir].fft_shape_out;
+      op->gemm_min_rhs[dir][p.gemv] = cross[dir];
       op->tuned_ms[dir] = best_t[dir];
     }
   }

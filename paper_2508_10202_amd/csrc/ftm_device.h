@@ -35,42 +35,48 @@ template <class T>
 __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
 
 // ---------------------------------------------------------------------------
-// Round-to-nearest-even into a binary format with p significand bits (the
-// implicit bit included), smallest normal exponent emin and largest finite
-// value maxv.  Values below the normal range are rounded on the subnormal
-// grid 2^(emin-p+1); values that round beyond maxv become infinities.  The
-// scalings by powers of two are exact (x is brought to at most p integer
-// bits and back), and rint rounds half-way cases to even.
-__device__ __forceinline__ double round_fmt(double x, int p, int emin, double maxv) {
-  // exponent of x (0 and non-finite x give -1; both pass through unchanged)
-  int e = __builtin_amdgcn_frexp_exp(x) - 1;
-  e = e < emin ? emin : e;
-  const double r = ldexp(rint(ldexp(x, p - 1 - e)), e - p + 1);
-  return fabs(r) > maxv ? copysign(__builtin_inf(), x) : r;
+// Round-to-nearest-even into the storage formats, branch free.
+//   float -> FP16: the hardware conversion (round to nearest even, subnormal
+//   results kept, overflow to infinity) and back.
+//   float -> BF16: BF16 is the top half of a float; adding 0x7fff plus the
+//   lowest kept bit to the bits and truncating rounds to nearest even
+//   (carries into the exponent give the next binade or infinity); NaN is kept.
+//   double -> FP16/BF16: round to odd into float first (truncate, then set the
+//   last bit if anything was dropped), then to nearest even: with float's 24
+//   bits at least two more than the target's, the two steps give the direct
+//   rounding (Boldo and Melquiond, IEEE TC 2008).
+__device__ __forceinline__ float round_f16(float x) { return __half2float(__float2half_rn(x)); }
+__device__ __forceinline__ float round_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const float r = __uint_as_float((u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u);
+  return x != x ? x : r;
 }
-__device__ __forceinline__ float round_fmt(float x, int p, int emin, float maxv) {
-  int e = __builtin_amdgcn_frexp_expf(x) - 1;
-  e = e < emin ? emin : e;
-  const float r = ldexpf(rintf(ldexpf(x, p - 1 - e)), e - p + 1);
-  return fabsf(r) > maxv ? copysignf(__builtin_inff(), x) : r;
+__device__ __forceinline__ float to_float_odd(double x) {
+  const float f = (float)x;
+  const double df = (double)f;
+  uint32_t u = __float_as_uint(f);
+  if (df != x && x == x) {
+    u -= fabs(df) > fabs(x) ? 1u : 0u;  // rounded away from zero: step back to the truncation
+    u |= 1u;                            // sticky: something was dropped
+  }
+  return __uint_as_float(u);
 }
 
-constexpr double F16_MAX = 65504.0;
-constexpr double BF16_MAX = 3.38953138925153547590470800371487866880e+38;
-
-// Value of x after storage in format dt (a value of the same C type).
+// Value of x after storage in format dt (a value of the same C type).  dt is
+// uniform across a launch, so the switch is a scalar branch and only one
+// format's rounding runs.
 __device__ __forceinline__ double round_to(double x, int dt) {
   switch (dt) {
     case DT_F32: return (double)(float)x;
-    case DT_F16: return round_fmt(x, 11, -14, F16_MAX);
-    case DT_BF16: return round_fmt(x, 8, -126, BF16_MAX);
+    case DT_F16: return (double)round_f16(to_float_odd(x));
+    case DT_BF16: return (double)round_bf16(to_float_odd(x));
     default: return x;
   }
 }
 __device__ __forceinline__ float round_to(float x, int dt) {
   switch (dt) {
-    case DT_F16: return round_fmt(x, 11, -14, (float)F16_MAX);
-    case DT_BF16: return round_fmt(x, 8, -126, (float)BF16_MAX);
+    case DT_F16: return round_f16(x);
+    case DT_BF16: return round_bf16(x);
     default: return x;
   }
 }

@@ -170,7 +170,12 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
   // load, rounded to the pad and FFT formats; series 2p -> real, 2p+1 -> imaginary
   {
     const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
-    const double* xs = xb + (live ? s : 0);
+    int64_t off = 0;
+    if (live) {
+      const int64_t rr = a.ncol >= a.S ? 0 : s / a.ncol;
+      off = rr * a.x_sr + (s - rr * a.ncol) * a.x_sc;
+    }
+    const double* xs = xb + off;
     const int64_t xstep = (int64_t)rstep * a.x_row_stride;
     TC* comp = reinterpret_cast<TC*>(lds) + (j & 1);
     const int zb = (j >> 1) * N;

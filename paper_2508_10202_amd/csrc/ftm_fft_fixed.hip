@@ -235,25 +235,37 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
   const int64_t b = wg / ntile, s0 = (wg - b * ntile) * C;
   const int tid = threadIdx.x, Nt = a.Nt;
 
-  // tile load: thread tid takes column c = tid mod C of rows tid / C + n ROWS;
-  // both series of a transform share its slab (real and imaginary parts)
+  // tile load: thread tid takes column c = tid mod C of rows tid / C + n ROWS
+  // (row-contiguous input), or, when time is the contiguous axis (a setup
+  // layout with series along memory), column tid / (WG / C) of rows
+  // tid mod (WG / C) + n WG / C; both series of a transform share its slab
+  // (real and imaginary parts)
   {
-    const int c = tid % C;
-    const bool live = s0 + c < a.S;
+    constexpr int TPC = WG / C;  // threads per column in the time-contiguous mapping
+    const bool tmajor = a.x_row_stride == 1 && a.S > 1;
+    const int c = tmajor ? tid / TPC : tid % C;
+    const int t_first = tmajor ? tid % TPC : tid / C, t_step = tmajor ? TPC : ROWS;
+    const int64_t s = s0 + c;
+    const bool live = s < a.S;
     const double* xb = a.xptr ? a.xptr[b] : a.x + b * a.x_rhs_stride;
-    const double* xs = xb + (live ? s0 + c : 0);
+    int64_t off = 0;
+    if (live) {
+      const int64_t rr = a.ncol >= a.S ? 0 : s / a.ncol;
+      off = rr * a.x_sr + (s - rr * a.ncol) * a.x_sc;
+    }
+    const double* xs = xb + off;
     TC* comp = reinterpret_cast<TC*>(slabs + (c / 2) * SL) + (c & 1);
     constexpr int U = 4;  // loads in flight per thread
-    for (int t0 = tid / C; t0 < Nt; t0 += U * ROWS) {
+    for (int t0 = t_first; t0 < Nt; t0 += U * t_step) {
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * ROWS;
+        const int t = t0 + u * t_step;
         v[u] = (live && t < Nt) ? xs[(int64_t)t * a.x_row_stride] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * ROWS;
+        const int t = t0 + u * t_step;
         if (t < Nt) comp[2 * lds_ix(t)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), a.r_fft);
       }
     }

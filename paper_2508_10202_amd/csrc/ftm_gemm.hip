@@ -9,12 +9,14 @@
 // is a real row of length 2*ld.  With X' = raw(X) and the two real variants
 // of the spectrum rows Fr' = (re, -im, re, -im, ..) and Fi' = (im, re, ..),
 // Re Y = X' Fr'^T and Im Y = X' Fi'^T: two real products over K' = 2 Nm.
-// A workgroup owns 64 right-hand sides x 64 rows of one frequency; X' is
-// staged through LDS in chunks of 64 reals and shared by the 4 waves, each
-// wave streams its own 16 spectrum rows from HBM.
+// A workgroup owns BM = 16, 32 or 64 right-hand sides (TB tiles of 16) x 64
+// rows of one frequency; X' is staged through LDS in chunks of 64 reals and
+// shared by the 4 waves, each wave streams its own 16 spectrum rows from HBM.
+// The right-hand-side tile follows the batch (a batch of 2 does not pay for
+// 64): the tile rows past nrhs are clamped copies, computed and not stored.
 //
 // Adjoint: the reduction runs over sensors r; each wave owns 16 columns c and
-// 64 right-hand sides (4 MFMA tiles).  Re Y = xr fr + xi fi and
+// BM right-hand sides (TB MFMA tiles).  Re Y = xr fr + xi fi and
 // Im Y = xi fr - xr fi, four real MFMAs per step.  X_k is small and shared
 // by every workgroup of the frequency, so it is read through the caches.
 //
@@ -31,7 +33,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int GEMM_THREADS = 256;
-constexpr int GEMM_BM = 64;  // right-hand sides per workgroup
 constexpr int FWD_BN = 64;   // spectrum rows per workgroup (forward)
 constexpr int ADJ_BN = 64;   // columns per workgroup (adjoint)
 constexpr int KC = 64;       // reals of K' per LDS chunk (forward)
@@ -85,17 +86,17 @@ __device__ __forceinline__ void store_c(float* y, float re, float im, int r_gemv
 #endif
 constexpr int GEMM_FWD_NW = FTM_GEMM_FWD_NW;
 
-template <int NW>
+template <int NW, int TB>
 __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
-  constexpr int TH = 64 * NW;
-  __shared__ float xs[GEMM_BM][KC + LDS_PAD];
+  constexpr int TH = 64 * NW, BM = 16 * TB;
+  __shared__ float xs[BM][KC + LDS_PAD];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * nrb;
   const int64_t k = wg / per_k;
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, r0 = (rb * NW + w) * 16;
+  const int b0 = bb * BM, r0 = (rb * NW + w) * 16;
   const int kr = 2 * a.ld;  // reals per row
 
   const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
@@ -104,13 +105,13 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
   const int r_me = min(r0 + l16, a.Nd - 1);  // clamped rows: computed, never stored
   const float* __restrict__ frow = Fk + (int64_t)r_me * kr;
 
-  f32x4 re[4], im[4];
+  f32x4 re[TB], im[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // cooperative X' staging: 64 rows x 64 reals = 1024 float4; float4 e goes
+  // cooperative X' staging: BM rows x 64 reals = 16 BM float4; float4 e goes
   // to row e / 16, reals 4 (e mod 16) .. +3, so 16 threads read one row's 256 B
-  constexpr int NST = 1024 / TH;
+  constexpr int NST = (16 * BM + TH - 1) / TH;
   const float* __restrict__ xsrc[NST];
   int st_row[NST], st_col[NST];
 #pragma unroll
@@ -118,13 +119,14 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
     const int e = threadIdx.x + TH * q;
     st_row[q] = e >> 4;
     st_col[q] = (e & 15) * 4;
-    xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
+    xsrc[q] = X + min(b0 + min(st_row[q], BM - 1), a.nrhs - 1) * xrow;
   }
 
   for (int kc = 0; kc < kr; kc += KC) {
-    // stage X'[b0..b0+64)[kc..kc+64) (zero past the row end)
+    // stage X'[b0..b0+BM)[kc..kc+64) (zero past the row end)
 #pragma unroll
     for (int q = 0; q < NST; ++q) {
+      if (16 * BM % TH != 0 && st_row[q] >= BM) continue;
       const int col = kc + st_col[q];
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (col < kr) v = *reinterpret_cast<const float4*>(xsrc[q] + col);
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
       const float br[4] = {f0, -f1, f2, -f3};  // (re, -im, ..)
       const float bi[4] = {f1, f0, f3, f2};    // (im, re, ..)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TB; ++t) {
         const float4 xa = *reinterpret_cast<const float4*>(&xs[16 * t + l16][16 * s + 4 * g]);
         const float av[4] = {xa.x, xa.y, xa.z, xa.w};
 #pragma unroll
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
@@ -179,18 +181,19 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
 // ---------------------------------------------------------------------------
 // forward, FP16/BF16 storage: MFMA 16x16x32 (K' = 32 reals per instruction)
 // ---------------------------------------------------------------------------
-template <class S>
+template <class S, int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, int nbb, int nrb) {
   using M = MfmaOf<S>;
   using H = typename M::half_t;
-  __shared__ uint16_t xs[GEMM_BM][KC + 8];  // X' in 16-bit, 64 reals per chunk
+  constexpr int BM = 16 * TB;
+  __shared__ uint16_t xs[BM][KC + 8];  // X' in 16-bit, 64 reals per chunk
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * nrb;
   const int64_t k = wg / per_k;
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, r0 = rb * FWD_BN + w * 16;
+  const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
   const int kr = 2 * a.ld;
 
   const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
@@ -199,27 +202,27 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   const int r_me = min(r0 + l16, a.Nd - 1);
   const uint16_t* __restrict__ frow = Fk + (int64_t)r_me * kr;
 
-  f32x4 re[4], im[4];
+  f32x4 re[TB], im[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // X' staging: float4 e (of 1024 per chunk) goes to row e / 16, reals
+  // X' staging: float4 e (of 16 BM per chunk) goes to row e / 16, reals
   // 4 (e mod 16) .. +3, so 16 threads read one row's 256 B.  Chunk kc + KC is
   // loaded into registers while the matrix cores work on chunk kc.
-  int st_row[4], st_col[4];
-  const float* __restrict__ xsrc[4];
+  int st_row[TB], st_col[TB];
+  const float* __restrict__ xsrc[TB];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < TB; ++q) {
     const int e = threadIdx.x + GEMM_THREADS * q;
     st_row[q] = e >> 4;
     st_col[q] = (e & 15) * 4;
     xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
   }
-  float4 xv[4];
+  float4 xv[TB];
   uint4 fn[2];
   auto load_chunk = [&](int kc) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < TB; ++q) {
       const int col = kc + st_col[q];
       xv[q] = col < kr ? *reinterpret_cast<const float4*>(xsrc[q] + col) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   load_chunk(0);
   for (int kc = 0; kc < kr; kc += KC) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < TB; ++q) {
       uint16_t* d = &xs[st_row[q]][st_col[q]];
       d[0] = (uint16_t)to_bits16<H>(xv[q].x);
       d[1] = (uint16_t)to_bits16<H>(xv[q].y);
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
       typename M::vec br = *reinterpret_cast<const typename M::vec*>(&ur);
       typename M::vec bi = *reinterpret_cast<const typename M::vec*>(&ui);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TB; ++t) {
         const typename M::vec xa = *reinterpret_cast<const typename M::vec*>(&xs[16 * t + l16][32 * s + 8 * g]);
         re[t] = M::mma(xa, br, re[t]);
         im[t] = M::mma(xa, bi, im[t]);
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
@@ -290,29 +293,31 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
 constexpr int RC = 32;
 
 // FP32 storage: MFMA 16x16x4 f32, 8 k-steps of 4 sensors per chunk.
+template <int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, int nbb, int ncb) {
+  constexpr int BM = 16 * TB, NX = BM * RC / GEMM_THREADS;  // data-tile loads per thread
   __shared__ cplx<float> fs[RC][ADJ_BN + 2];
-  __shared__ cplx<float> xs[GEMM_BM][RC + 1];
+  __shared__ cplx<float> xs[BM][RC + 1];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * ncb;
   const int64_t k = wg / per_k;
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / ncb, cb = rem - bb * ncb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN;
+  const int b0 = bb * BM, c0 = cb * ADJ_BN;
 
   const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
   const cplx<float>* __restrict__ Fk = reinterpret_cast<const cplx<float>*>(a.F) + k * a.f_k_stride;
 
-  f32x4 re[4], im[4];
+  f32x4 re[TB], im[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
   // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
   // on chunk r0: the spectrum tile (32 rows x 64 columns, two complex per
-  // 16-byte load) and the data tile (64 right-hand sides x 32 sensors).
+  // 16-byte load) and the data tile (BM right-hand sides x 32 sensors).
   float4 fv[4];
-  cplx<float> xv[8];
+  cplx<float> xv[NX];
   auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
                                       : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
       fs[row][col + 1] = {fv[q].z, fv[q].w};
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       xs[idx >> 5][idx & 31] = xv[q];
     }
@@ -350,7 +355,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
     for (int s = 0; s < RC / 4; ++s) {
       const cplx<float> f = fs[4 * s + g][w * 16 + l16];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TB; ++t) {
         const cplx<float> x = xs[16 * t + l16][4 * s + g];
         re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, f.x, re[t], 0, 0, 0);
         re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, f.y, re[t], 0, 0, 0);
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
@@ -374,33 +379,34 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
 }
 
 // FP16/BF16 storage: MFMA 16x16x32, one k-step of 32 sensors per chunk.
-template <class S>
+template <class S, int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, int nbb, int ncb) {
   using M = MfmaOf<S>;
   using H = typename M::half_t;
+  constexpr int BM = 16 * TB, NX = BM * RC / GEMM_THREADS;  // data-tile loads per thread
   __shared__ uint32_t fs[RC][ADJ_BN + 4];            // (re | im << 16) per complex
-  __shared__ __align__(16) uint16_t xr16[GEMM_BM][RC + 8];
-  __shared__ __align__(16) uint16_t xi16[GEMM_BM][RC + 8];
+  __shared__ __align__(16) uint16_t xr16[BM][RC + 8];
+  __shared__ __align__(16) uint16_t xi16[BM][RC + 8];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * ncb;
   const int64_t k = wg / per_k;
   const int rem = (int)(wg - k * per_k);
   const int bb = rem / ncb, cb = rem - bb * ncb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
-  const int b0 = bb * GEMM_BM, c0 = cb * ADJ_BN;
+  const int b0 = bb * BM, c0 = cb * ADJ_BN;
 
   const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
   const uint32_t* __restrict__ Fk = reinterpret_cast<const uint32_t*>(a.F) + k * a.f_k_stride;
 
-  f32x4 re[4], im[4];
+  f32x4 re[TB], im[TB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
   // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
   // on chunk r0: the spectrum tile (32 rows x 64 columns, four complex per
-  // 16-byte load) and the data tile (64 right-hand sides x 32 sensors).
+  // 16-byte load) and the data tile (BM right-hand sides x 32 sensors).
   uint4 fv[2];
-  cplx<float> xv[8];
+  cplx<float> xv[NX];
   auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
       fv[q] = (r < a.Nd && c < a.ld) ? load_stream(Fk + (int64_t)r * a.ld + c) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
@@ -429,7 +435,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
       fs[row][col + 3] = fv[q].w;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
       xr16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].x);  // exact: x holds values of the 16-bit format
@@ -450,7 +456,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
     const typename M::vec fr = __builtin_bit_cast(typename M::vec, ufr);
     const typename M::vec fi = __builtin_bit_cast(typename M::vec, ufi);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TB; ++t) {
       const uint4 uxr = *reinterpret_cast<const uint4*>(&xr16[16 * t + l16][8 * g]);
       const uint4 uxi = *reinterpret_cast<const uint4*>(&xi16[16 * t + l16][8 * g]);
       const uint4 uxn = make_uint4(uxr.x ^ 0x80008000u, uxr.y ^ 0x80008000u, uxr.z ^ 0x80008000u,
@@ -470,7 +476,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TB; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
@@ -478,16 +484,207 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// float64 accumulation: MFMA 16x16x4 f64, from float64 storage (an all-FP64
+// product) or FP32 storage (FP32 values, products exact in float64; the
+// +a64 configurations).  The transformed vectors are float64 or float32 as the
+// neighbouring phases store them (TX in, TY out).  Same tilings as the FP32
+// kernels; a 16-byte load carries RPL = 16 / sizeof(TF) reals of the spectrum.
+// Lane layout of 16x16x4 f64 (checked on gfx950): A[i][k] in lane i + 16 k and
+// B[k][j] in lane j + 16 k as for 16x16x4 f32, but D[4 v + g][j] in lane
+// j + 16 g, element v (f32: D[4 g + v][j]).
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store_c64(double* y, double re, double im, int, int) {
+  *reinterpret_cast<double2*>(y) = make_double2(re, im);
+}
+__device__ __forceinline__ void store_c64(float* y, double re, double im, int r_gemv, int r_next) {
+  *reinterpret_cast<float2*>(y) = make_float2((float)round_to(round_to(re, r_gemv), r_next),
+                                              (float)round_to(round_to(im, r_gemv), r_next));
+}
+
+template <class TF, class TX, class TY, int TB>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_a64_kernel(GemvArgs a, int nbb, int nrb) {
+  constexpr int BM = 16 * TB, RPL = 16 / sizeof(TF), KC64 = 16 * RPL;  // reals per chunk
+  __shared__ double xs[BM][KC64 + 2];
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * nrb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / nrb, rb = rem - bb * nrb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
+  const int kr = 2 * a.ld;
+
+  const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + 2 * k * a.x_k_stride;
+  const int64_t xrow = 2 * a.x_rhs_stride;
+  const TF* __restrict__ Fk = reinterpret_cast<const TF*>(a.F) + 2 * k * a.f_k_stride;
+  const int r_me = min(r0 + l16, a.Nd - 1);  // clamped rows: computed, never stored
+  const TF* __restrict__ frow = Fk + (int64_t)r_me * kr;
+
+  f64x4 re[TB], im[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+  // X' staging, two reals per thread and step: BM rows x KC64 reals
+  constexpr int NPAIR = BM * KC64 / 2, NST = (NPAIR + GEMM_THREADS - 1) / GEMM_THREADS;
+  for (int kc = 0; kc < kr; kc += KC64) {
+#pragma unroll
+    for (int q = 0; q < NST; ++q) {
+      const int e = threadIdx.x + GEMM_THREADS * q;
+      if (NPAIR % GEMM_THREADS != 0 && e >= NPAIR) continue;
+      const int row = e / (KC64 / 2), col = 2 * (e % (KC64 / 2));
+      const TX* src = X + min(b0 + row, a.nrhs - 1) * xrow + kc + col;
+      double v0 = 0.0, v1 = 0.0;
+      if (kc + col < kr) {
+        v0 = (double)src[0];
+        v1 = (double)src[1];
+      }
+      xs[row][col] = v0;
+      xs[row][col + 1] = v1;
+    }
+    // this wave's spectrum rows: lane (l16, g) holds reals kc + RPL (4 s + g) ..
+    uint4 fv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int col = kc + RPL * (4 * s + g);
+      fv[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double f[RPL];
+      if constexpr (RPL == 2) {
+        const double2 d = __builtin_bit_cast(double2, fv[s]);
+        f[0] = d.x;
+        f[1] = d.y;
+      } else {
+        f[0] = (double)__uint_as_float(fv[s].x);
+        f[1] = (double)__uint_as_float(fv[s].y);
+        f[2] = (double)__uint_as_float(fv[s].z);
+        f[3] = (double)__uint_as_float(fv[s].w);
+      }
+#pragma unroll
+      for (int v = 0; v < RPL; ++v) {
+        // (re, -im, ..) and (im, re, ..) of the complex pair this real belongs to
+        const double br = (v & 1) ? -f[v] : f[v];
+        const double bi = (v & 1) ? f[v - 1] : f[v + 1];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+          const double xa = xs[16 * t + l16][RPL * (4 * s + g) + v];
+          re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, br, re[t], 0, 0, 0);
+          im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, bi, im[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const int r = r0 + l16;
+  if (r >= a.Nd) return;
+  TY* Y = reinterpret_cast<TY*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * v + g;  // D[4 v + g][j] of 16x16x4 f64
+      if (b < a.nrhs) store_c64(Y + 2 * (b * a.y_rhs_stride + r), re[t][v], im[t][v], a.r_gemv, a.r_next);
+    }
+}
+
+// adjoint with float64 accumulation: chunks of RC64 = 16 sensors through LDS
+constexpr int RC64 = 16;
+
+template <class TF, class TX, class TY, int TB>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_a64_kernel(GemvArgs a, int nbb, int ncb) {
+  constexpr int BM = 16 * TB;
+  __shared__ cplx<double> fs[RC64][ADJ_BN + 1];
+  __shared__ cplx<double> xs[BM][RC64 + 1];
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * ncb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / ncb, cb = rem - bb * ncb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * BM, c0 = cb * ADJ_BN;
+
+  const cplx<TX>* __restrict__ X = reinterpret_cast<const cplx<TX>*>(a.x) + k * a.x_k_stride;
+  const cplx<TF>* __restrict__ Fk = reinterpret_cast<const cplx<TF>*>(a.F) + k * a.f_k_stride;
+
+  f64x4 re[TB], im[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+  constexpr int NF = RC64 * ADJ_BN / GEMM_THREADS, NX = (BM * RC64 + GEMM_THREADS - 1) / GEMM_THREADS;
+  for (int r0 = 0; r0 < a.Nd; r0 += RC64) {
+    // spectrum tile RC64 x 64 (one complex per thread and step, coalesced rows)
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx / ADJ_BN, col = idx % ADJ_BN;
+      const int r = r0 + row, c = c0 + col;
+      cplx<TF> f = {(TF)0, (TF)0};
+      if (r < a.Nd && c < a.ld) f = Fk[(int64_t)r * a.ld + c];
+      fs[row][col] = {(double)f.x, (double)f.y};
+    }
+    // data tile BM right-hand sides x RC64 sensors (sensors past Nd are zero)
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      if ((BM * RC64) % GEMM_THREADS != 0 && idx >= BM * RC64) continue;
+      const int bl = idx / RC64, rr = idx % RC64;
+      const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
+      cplx<TX> x = {(TX)0, (TX)0};
+      if (r < a.Nd) x = X[(int64_t)b * a.x_rhs_stride + r];
+      xs[bl][rr] = {(double)x.x, (double)x.y};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < RC64 / 4; ++s) {
+      const cplx<double> f = fs[4 * s + g][w * 16 + l16];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        const cplx<double> x = xs[16 * t + l16][4 * s + g];
+        re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, f.x, re[t], 0, 0, 0);
+        re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, f.y, re[t], 0, 0, 0);
+        im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, f.x, im[t], 0, 0, 0);
+        im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x.x, f.y, im[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int c = c0 + w * 16 + l16;
+  if (c >= a.Nm) return;
+  TY* Y = reinterpret_cast<TY*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * v + g;  // D[4 v + g][j] of 16x16x4 f64
+      if (b < a.nrhs) store_c64(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
+    }
+}
+
 // ---- host launchers -----------------------------------------------------------
 
-hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st) {
-  const int nbb = (a.nrhs + GEMM_BM - 1) / GEMM_BM;
+// Right-hand sides per tile: the asked one (16, 32 or 64), else the
+// smallest of them that holds the batch, capped at 64.
+static int rhs_tile(const GemvArgs& a) {
+  if (a.rhs_tile == 16 || a.rhs_tile == 32 || a.rhs_tile == 64) return a.rhs_tile;
+  return a.nrhs <= 16 ? 16 : (a.nrhs <= 32 ? 32 : 64);
+}
+
+template <int TB>
+static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
+  const int nbb = (a.nrhs + 16 * TB - 1) / (16 * TB);
   if (fdt == DT_F32) {
     const int nrb = (a.Nd + 16 * GEMM_FWD_NW - 1) / (16 * GEMM_FWD_NW);
     const int64_t nwg = (int64_t)a.K * nbb * nrb;
     if (nwg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gemm_fwd_f32_kernel<GEMM_FWD_NW>, dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0, st, a, nbb,
-                       nrb);
+    hipLaunchKernelGGL((gemm_fwd_f32_kernel<GEMM_FWD_NW, TB>), dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0, st, a,
+                       nbb, nrb);
     return hipGetLastError();
   }
   const int nrb = (a.Nd + FWD_BN - 1) / FWD_BN;
@@ -495,25 +692,76 @@ hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
-    case DT_F16: hipLaunchKernelGGL(gemm_fwd_h_kernel<s_f16>, grid, block, 0, st, a, nbb, nrb); break;
-    case DT_BF16: hipLaunchKernelGGL(gemm_fwd_h_kernel<s_bf16>, grid, block, 0, st, a, nbb, nrb); break;
+    case DT_F16: hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, nrb); break;
+    case DT_BF16: hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, nrb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_adj(int fdt, const GemvArgs& a, hipStream_t st) {
-  const int nbb = (a.nrhs + GEMM_BM - 1) / GEMM_BM, ncb = (a.Nm + ADJ_BN - 1) / ADJ_BN;
+template <int TB>
+static hipError_t gemm_adj_go(int fdt, const GemvArgs& a, hipStream_t st) {
+  const int nbb = (a.nrhs + 16 * TB - 1) / (16 * TB), ncb = (a.Nm + ADJ_BN - 1) / ADJ_BN;
   const int64_t nwg = (int64_t)a.K * nbb * ncb;
   if (nwg <= 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
-    case DT_F32: hipLaunchKernelGGL(gemm_adj_f32_kernel, grid, block, 0, st, a, nbb, ncb); break;
-    case DT_F16: hipLaunchKernelGGL(gemm_adj_h_kernel<s_f16>, grid, block, 0, st, a, nbb, ncb); break;
-    case DT_BF16: hipLaunchKernelGGL(gemm_adj_h_kernel<s_bf16>, grid, block, 0, st, a, nbb, ncb); break;
+    case DT_F32: hipLaunchKernelGGL((gemm_adj_f32_kernel<TB>), grid, block, 0, st, a, nbb, ncb); break;
+    case DT_F16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, ncb); break;
+    case DT_BF16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, ncb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <class TF, class TX, class TY, int TB>
+static hipError_t gemm_a64_go(bool adjoint, const GemvArgs& a, hipStream_t st) {
+  const int nbb = (a.nrhs + 16 * TB - 1) / (16 * TB);
+  const int nb2 = adjoint ? (a.Nm + ADJ_BN - 1) / ADJ_BN : (a.Nd + FWD_BN - 1) / FWD_BN;
+  const int64_t nwg = (int64_t)a.K * nbb * nb2;
+  if (nwg <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
+  if (adjoint) hipLaunchKernelGGL((gemm_adj_a64_kernel<TF, TX, TY, TB>), grid, block, 0, st, a, nbb, nb2);
+  else hipLaunchKernelGGL((gemm_fwd_a64_kernel<TF, TX, TY, TB>), grid, block, 0, st, a, nbb, nb2);
+  return hipGetLastError();
+}
+
+template <class TF>
+static hipError_t gemm_a64_types(bool adjoint, bool in64, bool out64, const GemvArgs& a, int tb, hipStream_t st) {
+#define FTM_A64(TX, TY)                                                          \
+  switch (tb) {                                                                  \
+    case 16: return gemm_a64_go<TF, TX, TY, 1>(adjoint, a, st);                  \
+    case 32: return gemm_a64_go<TF, TX, TY, 2>(adjoint, a, st);                  \
+    default: return gemm_a64_go<TF, TX, TY, 4>(adjoint, a, st);                  \
+  }
+  if (in64 && out64) { FTM_A64(double, double) }
+  if (in64) { FTM_A64(double, float) }
+  if (out64) { FTM_A64(float, double) }
+  FTM_A64(float, float)
+#undef FTM_A64
+}
+
+hipError_t launch_gemm_a64(bool adjoint, int fdt, bool in64, bool out64, const GemvArgs& a, hipStream_t st) {
+  const int tb = rhs_tile(a);
+  if (fdt == DT_F64) return gemm_a64_types<double>(adjoint, in64, out64, a, tb, st);
+  if (fdt == DT_F32) return gemm_a64_types<float>(adjoint, in64, out64, a, tb, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st) {
+  switch (rhs_tile(a)) {
+    case 16: return gemm_fwd_go<1>(fdt, a, st);
+    case 32: return gemm_fwd_go<2>(fdt, a, st);
+    default: return gemm_fwd_go<4>(fdt, a, st);
+  }
+}
+
+hipError_t launch_gemm_adj(int fdt, const GemvArgs& a, hipStream_t st) {
+  switch (rhs_tile(a)) {
+    case 16: return gemm_adj_go<1>(fdt, a, st);
+    case 32: return gemm_adj_go<2>(fdt, a, st);
+    default: return gemm_adj_go<4>(fdt, a, st);
+  }
 }
 
 }  // namespace ftm

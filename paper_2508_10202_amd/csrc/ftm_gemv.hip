@@ -371,6 +371,19 @@ static dim3 grid_for(int64_t n) {
   return dim3((unsigned)g);
 }
 
+// The kernels' rounding of values into storage format dt (from float64, or
+// from float32 after a round-to-nearest-even into float32 when from_f32).
+__global__ void round_values_kernel(int dt, int from_f32, const double* __restrict__ x, double* __restrict__ y,
+                                    int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = from_f32 ? (double)round_to((float)x[i], dt) : round_to(x[i], dt);
+}
+
+hipError_t launch_round_values(int dt, bool from_f32, const double* x, double* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(round_values_kernel, grid_for(n), dim3(256), 0, st, dt, from_f32 ? 1 : 0, x, y, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_store_spectrum(const void* src, int dt, void* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(store_spectrum_kernel, grid_for(n), dim3(256), 0, st,
                      reinterpret_cast<const cplx<double>*>(src), dt, dst, n);

@@ -58,7 +58,7 @@ struct FftPlan {
 };
 
 // Phases 1+2 (or the setup transform of F): real series x[b][t][s] (t < Nt,
-// s < S), zero padded to N = plan.N, transformed, bins k = 0 .. N/2 written to
+// s < S; addressing below), zero padded to N = plan.N, transformed, bins k = 0 .. N/2 written to
 // out[k * out_k_stride + b * out_rhs_stride + (s / ncol) * ld_row + s % ncol].
 // With xptr set (device array of nrhs pointers) right-hand side b is read from
 // xptr[b] instead of x + b * x_rhs_stride.  Columns S .. pad_to-1 of every
@@ -68,6 +68,9 @@ struct RfftArgs {
   const double* const* xptr;
   int64_t pad_to;
   int64_t x_rhs_stride, x_row_stride;
+  // series s of a right-hand side starts at x + (s / ncol) * x_sr +
+  // (s mod ncol) * x_sc (x_sc = 1 with ncol >= S: consecutive columns)
+  int64_t x_sr, x_sc;
   int64_t S;
   int Nt, nrhs;
   void* out;
@@ -101,7 +104,8 @@ struct GemvArgs {
   void* y;
   int64_t y_k_stride, y_rhs_stride;
   int r_gemv, r_next;
-  int variant;  // kernel variant (tile shape), 0 = default; see ftm_gemv.hip
+  int variant;   // kernel variant (tile shape), 0 = default; see ftm_gemv.hip
+  int rhs_tile;  // right-hand sides per GEMM tile: 16, 32 or 64 (0: by nrhs)
 };
 
 // Number of tile-shape variants of the matrix-vector kernels.
@@ -128,6 +132,12 @@ hipError_t launch_gemv_adj(int fdt, bool acc64, bool in64, bool out64, const Gem
 // storage, float32 accumulation; float32 transformed vectors).
 hipError_t launch_gemm_fwd(int fdt, const GemvArgs& a, hipStream_t st);
 hipError_t launch_gemm_adj(int fdt, const GemvArgs& a, hipStream_t st);
+// Phase 3 for many right-hand sides with float64 accumulation on the matrix
+// cores (FP64 or FP32 storage; float64 or float32 transformed vectors in/out).
+hipError_t launch_gemm_a64(bool adjoint, int fdt, bool in64, bool out64, const GemvArgs& a, hipStream_t st);
+// Round n float64 values into storage format dt as the kernels do (from
+// float32 after rounding to it, when from_f32).
+hipError_t launch_round_values(int dt, bool from_f32, const double* x, double* y, int64_t n, hipStream_t st);
 // Round a float64 complex spectrum to storage format dt (n complex numbers).
 hipError_t launch_store_spectrum(const void* src, int dt, void* dst, int64_t n, hipStream_t st);
 // Widen rows x ncol complex numbers of storage format dt (row stride ld) to a

@@ -177,19 +177,33 @@ def test_spectrum_storage_formats(gpu):
 
 
 def test_multi_rhs_matches_single_bitwise(gpu):
+    """One vector at a time (FTM_RHS_GEMV): a batch equals its vectors run
+    alone, bitwise.  The matrix-core path (the default for batches, float64
+    accumulation here) is batch invariant: a vector's result does not depend
+    on the batch around it or on the right-hand-side tile, bitwise; both
+    within 1e-12 of the oracle."""
     import torch
     from paper_2508_10202_amd import Operator
     s = Shape(40, 10, 200)
-    F, M, D = make_F(s, 51), make_m(s, 52, nrhs=3), make_d(s, 53, nrhs=3)
-    op = Operator(torch.from_numpy(F).cuda(), max_rhs=4)
+    F, M, D = make_F(s, 51), make_m(s, 52, nrhs=40), make_d(s, 53, nrhs=40)
+    op = Operator(torch.from_numpy(F).cuda(), max_rhs=40)
     Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
-    batch_d, batch_m = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
+    op.set_rhs_mode("gemv")
+    batch_d, batch_m = op.matvec(Mt[:3]).cpu().numpy(), op.rmatvec(Dt[:3]).cpu().numpy()
     for b in range(3):
         assert np.array_equal(batch_d[b], op.matvec(Mt[b]).cpu().numpy())
         assert np.array_equal(batch_m[b], op.rmatvec(Dt[b]).cpu().numpy())
+    assert _rel(batch_d, oracle.forward(F, M[:3])) <= FP64_TOL
+    assert _rel(batch_m, oracle.adjoint(F, D[:3])) <= FP64_TOL
+    op.set_rhs_mode("auto")
+    ref_d, ref_m = oracle.forward(F, M), oracle.adjoint(F, D)
+    g3d, g3m = op.matvec(Mt[:3]).cpu().numpy(), op.rmatvec(Dt[:3]).cpu().numpy()
+    for n, tile in ((40, 0), (40, 16), (17, 32), (5, 64)):
+        op.set_tuning(gemm_tile=(tile, tile))
+        gd, gm = op.matvec(Mt[:n]).cpu().numpy(), op.rmatvec(Dt[:n]).cpu().numpy()
+        assert np.array_equal(gd[:3], g3d) and np.array_equal(gm[:3], g3m), (n, tile)
+        assert _rel(gd, ref_d[:n]) <= FP64_TOL and _rel(gm, ref_m[:n]) <= FP64_TOL
     op.close()
-    assert _rel(batch_d, oracle.forward(F, M)) <= FP64_TOL
-    assert _rel(batch_m, oracle.adjoint(F, D)) <= FP64_TOL
 
 
 def test_apply_on_caller_workspaces_concurrently(gpu):
@@ -369,7 +383,7 @@ def test_paper_shape_mixed(gpu, paper_case):
 
 # --- many right-hand sides: the matrix-core GEMM path ---------------------------------
 
-GEMM_PRECS = ["ddsdd", "sssss", "ddhdd", "ddbdd", "dhhhd", "dbbbd"]
+GEMM_PRECS = ["ddsdd", "sssss", "ddhdd", "ddbdd", "dhhhd", "dbbbd", "ddddd", "ddsdd+a64", "sdsds+a64"]
 
 
 @pytest.fixture(scope="module")
@@ -380,30 +394,40 @@ def gemm_case():
     return s, F, M, D, oracle.forward(F, M), oracle.adjoint(F, D)
 
 
+def _gemm_bounds(prec, L, n):
+    lo, hi = mp_bounds(prec, L, n)
+    return (lo, FP64_TOL) if prec == "ddddd" else (lo, hi)
+
+
 @pytest.mark.parametrize("prec", GEMM_PRECS)
-@pytest.mark.parametrize("nrhs", [2, 17, 70])
+@pytest.mark.parametrize("nrhs", [2, 17, 33, 70])
 def test_gemm_path_vs_oracle(gpu, gemm_case, prec, nrhs):
-    """Forced GEMM path (ragged in every tile dimension) against the oracle, and
-    against the one-vector-at-a-time path of the same configuration."""
+    """Forced GEMM path (ragged in every tile dimension) for every right-hand-side
+    tile (16, 32, 64, and the default for the batch) against the oracle, every
+    right-hand side checked, and against the one-vector-at-a-time path of the
+    same configuration.  float64 products and +a64 ones accumulate in float64
+    on the matrix cores."""
     import torch
     from paper_2508_10202_amd import Operator
     s, F, M, D, ref_d, ref_m = gemm_case
-    _say("case gemm", prec, nrhs)
     op = Operator(torch.from_numpy(F).cuda(), fwd=prec, adj=prec, max_rhs=nrhs)
     Mt, Dt = torch.from_numpy(M[:nrhs].copy()).cuda(), torch.from_numpy(D[:nrhs].copy()).cuda()
-    op.set_rhs_mode("gemm")
-    gd, gm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
     op.set_rhs_mode("gemv")
     vd, vm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
+    op.set_rhs_mode("gemm")
+    lo_f, hi_f = _gemm_bounds(prec, s.L, s.Nm)
+    lo_a, hi_a = _gemm_bounds(prec, s.L, s.Nd)
+    for tile in (0, 16, 32, 64):
+        _say("case gemm", prec, nrhs, "tile", tile)
+        op.set_tuning(gemm_tile=(tile, tile))
+        gd, gm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
+        e_f, e_a = _rel(gd, ref_d[:nrhs]), _rel(gm, ref_m[:nrhs])
+        _say(f"  gemm {prec} nrhs={nrhs} tile={tile}: fwd {e_f:.3e} adj {e_a:.3e}; gemv fwd {_rel(vd, ref_d[:nrhs]):.3e}")
+        assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
+        for b in range(nrhs):                 # every right-hand side, not just the norm
+            assert _rel(gd[b], ref_d[b]) <= hi_f and _rel(gm[b], ref_m[b]) <= hi_a
+        assert _rel(gd, vd) <= 2 * hi_f and _rel(gm, vm) <= 2 * hi_a
     op.close()
-    lo_f, hi_f = mp_bounds(prec, s.L, s.Nm)
-    lo_a, hi_a = mp_bounds(prec, s.L, s.Nd)
-    e_f, e_a = _rel(gd, ref_d[:nrhs]), _rel(gm, ref_m[:nrhs])
-    _say(f"  gemm {prec} nrhs={nrhs}: fwd {e_f:.3e} adj {e_a:.3e}; gemv fwd {_rel(vd, ref_d[:nrhs]):.3e}")
-    assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
-    for b in range(nrhs):                     # every right-hand side, not just the norm
-        assert _rel(gd[b], ref_d[b]) <= hi_f and _rel(gm[b], ref_m[b]) <= hi_a
-    assert _rel(gd, vd) <= 2 * hi_f and _rel(gm, vm) <= 2 * hi_a
 
 
 def test_gemm_multi_rhs_shape(gpu):
@@ -415,17 +439,58 @@ def test_gemm_multi_rhs_shape(gpu):
     s, F, M, D = config_inputs("multi_rhs", nrhs=MULTI_RHS_NRHS)
     pick = [0, 21, 42, 63]
     ref_d, ref_m = oracle.forward(F, M[pick]), oracle.adjoint(F, D[pick])
-    op = Operator(torch.from_numpy(F).cuda(), fwd="ddsdd", adj="ddsdd", spectra=("b",), max_rhs=64)
+    op = Operator(torch.from_numpy(F).cuda(), fwd="ddsdd", adj="ddsdd", spectra=("b", "d"), max_rhs=64)
     Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
-    for prec in ("ddsdd", "dbbbd"):
+    for prec in ("ddsdd", "dbbbd", "ddddd", "ddsdd+a64"):
         _say("case multi-rhs", prec)
         op.set_precision(fwd=prec, adj=prec)
         gd, gm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
         e_f, e_a = _rel(gd[pick], ref_d), _rel(gm[pick], ref_m)
-        lo_f, hi_f = mp_bounds(prec, s.L, s.Nm)
-        lo_a, hi_a = mp_bounds(prec, s.L, s.Nd)
+        lo_f, hi_f = _gemm_bounds(prec, s.L, s.Nm)
+        lo_a, hi_a = _gemm_bounds(prec, s.L, s.Nd)
         _say(f"  multi-rhs {prec}: fwd {e_f:.3e} [{lo_f:.1e},{hi_f:.1e}] adj {e_a:.3e} [{lo_a:.1e},{hi_a:.1e}]")
         assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
+    op.close()
+
+
+# --- data-space Hessian actions F F^T ----------------------------------------------------
+
+@pytest.mark.parametrize("prec,nrhs,s", [
+    ("ddddd", 3, Shape(64, 16, 256)),
+    ("ddddd", 1, Shape(45, 13, 301, decay=30.0)),
+    ("ddddd", 5, Shape(100, 37, 1000)),        # float64 matrix-core path for both directions
+    ("dssdd", 20, Shape(100, 37, 1000)),       # float32 matrix-core path
+    ("ddsdd+a64", 20, Shape(64, 40, 300, decay=50.0)),
+])
+def test_hessian_actions_vs_oracle(gpu, prec, nrhs, s):
+    """y = F F^T x through ftm_hessian_apply against the oracle's definition,
+    every right-hand side, plus the symmetry <Hx, z> = <x, Hz> on the GPU's own
+    outputs."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    _say("case hessian", prec, nrhs, s)
+    F = make_F(s, 121)
+    X, Z = make_d(s, 122, nrhs=nrhs), make_d(s, 123, nrhs=nrhs)
+    op = Operator(torch.from_numpy(F).cuda(), fwd=prec, adj=prec, max_rhs=nrhs)
+    Xt, Zt = torch.from_numpy(X).cuda(), torch.from_numpy(Z).cuda()
+    ws = torch.full(((op.hessian_workspace_size(nrhs) + 7) // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    hx = op.hessian(Xt, workspace=ws).cpu().numpy()
+    hz = op.hessian(Zt).cpu().numpy()
+    ref = oracle.hessian_data_space(F, X)
+    tol = FP64_TOL if prec == "ddddd" else mp_bounds(prec, s.L, s.Nd)[1] + mp_bounds(prec, s.L, s.Nm)[1]
+    e = _rel(hx, ref)
+    _say(f"  hessian {prec}: {e:.3e} <= {tol:.1e}")
+    assert e <= tol
+    for b in range(nrhs):
+        assert _rel(hx[b], ref[b]) <= tol
+    lhs, rhs = float(np.vdot(hx, Z)), float(np.vdot(X, hz))
+    assert abs(lhs - rhs) <= 4 * tol * (abs(lhs) + abs(rhs))
+    from paper_2508_10202_amd import FtmError
+    with pytest.raises(FtmError):                # a workspace one byte short
+        from paper_2508_10202_amd import _lib
+        out = torch.empty_like(Xt)
+        _lib.check(_lib.lib().ftm_hessian_apply(op.handle, Xt.data_ptr(), out.data_ptr(), nrhs, ws.data_ptr(),
+                                                op.hessian_workspace_size(nrhs) - 1, None), "ftm_hessian_apply")
     op.close()
 
 
@@ -475,6 +540,7 @@ def test_autotune_keeps_results_and_caches(gpu, tmp_path):
         assert not rec["cached"] and all(0 <= v < 4 for v in rec["gemv_variant"])
         assert all(0 <= v <= FFT_GENERIC for r in rec["fft_shape"] for v in r)
         assert all(t > 0 for t in rec["ms"])
+        assert all(2 <= c <= 33 for c in rec["gemm_min_rhs"])
         assert op.autotune(cache=cache)["cached"]
         mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
         ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
@@ -496,3 +562,117 @@ def test_autotune_keeps_results_and_caches(gpu, tmp_path):
         with pytest.raises(FtmError):
             op.set_tuning(fft_shape=((4, 0), (0, 0)))
         op.close()
+
+
+# --- rounding into the storage formats ---------------------------------------------------
+
+def _rne_ref(x, fmt):
+    """Round to nearest, ties to even, by the definition: scale by the format's
+    quantum at x's binade (exact powers of two), numpy.rint (ties to even) and
+    scale back; beyond the largest finite value, infinity."""
+    x = np.asarray(x, dtype=np.float64)
+    if fmt == "d":
+        return x.copy()
+    if fmt == "s":
+        with np.errstate(over="ignore"):
+            return x.astype(np.float32).astype(np.float64)
+    p, emin, vmax = (11, -14, 65504.0) if fmt == "h" else (8, -126, float.fromhex("0x1.fep127"))
+    out = x.copy()
+    fin = np.isfinite(x) & (x != 0)
+    _, e = np.frexp(x[fin])
+    E = np.maximum(e - 1, emin)
+    q = np.ldexp(1.0, E - (p - 1))
+    r = np.rint(x[fin] / q) * q
+    r = np.where(np.abs(r) > vmax, np.copysign(np.inf, x[fin]), r)
+    out[fin] = r
+    return out
+
+
+def _rounding_cases():
+    rng = np.random.default_rng(131)
+    v = [rng.standard_normal(20000) * 10.0 ** rng.uniform(-44, 38, 20000)]
+    # exact bfloat16 ties (low 16 bits 0x8000) and just off them in float64
+    bits = (rng.integers(0x00800000, 0x7f000000, 4000, dtype=np.int64) & ~0xffff) | 0x8000
+    ties_b = bits.astype(np.uint32).view(np.float32).astype(np.float64)
+    v += [ties_b, -ties_b, ties_b * (1 + 2.0 ** -40), ties_b * (1 - 2.0 ** -40)]
+    # exact FP16 ties (midpoints of neighbours, subnormal range included) and just off them
+    with np.errstate(over="ignore"):
+        h = np.sort(np.abs(rng.standard_normal(4000) * 10.0 ** rng.uniform(-7, 4.8, 4000))).astype(np.float16)
+    hn = np.nextafter(h, np.float16(np.inf))
+    mid = (h.astype(np.float64) + hn.astype(np.float64)) / 2
+    mid = mid[np.isfinite(mid)]
+    v += [mid, -mid, mid * (1 + 2.0 ** -40), mid * (1 - 2.0 ** -40)]
+    v.append(np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 65504.0, 65519.99, 65520.0, 65536.0, 1e-8, 5.96e-8,
+                       2.98e-8, 2.99e-8, float.fromhex("0x1.fep127"), float.fromhex("0x1.ffp127"),
+                       float.fromhex("0x1.fefffffffffffp127"), 3.4e38, 1e-45, 1e-40, 1e300, -1e300]))
+    return np.concatenate(v)
+
+
+@pytest.mark.parametrize("fmt", ["s", "h", "b"])
+@pytest.mark.parametrize("from_f32", [False, True])
+def test_rounding_matches_round_to_nearest_even(gpu, fmt, from_f32):
+    """The kernels' rounding into FP32/FP16/BF16 (ftm_round, the same device
+    functions every phase uses) equals round-to-nearest-even by its
+    definition, bitwise: ties, values just off ties in float64, subnormals,
+    overflow to infinity, infinities and NaN; from float64 directly, and from
+    float32 (the float32-compute phases)."""
+    import torch
+    from paper_2508_10202_amd import round_values
+    x = _rounding_cases()
+    got = round_values(torch.from_numpy(x).cuda(), fmt, from_f32=from_f32).cpu().numpy()
+    src = _rne_ref(x, "s") if from_f32 else x
+    want = _rne_ref(src, fmt)
+    same = (got == want) | (np.isnan(got) & np.isnan(want))
+    assert same.all(), (x[~same][:5], got[~same][:5], want[~same][:5])
+    assert np.array_equal(np.signbit(got[~np.isnan(got)]), np.signbit(want[~np.isnan(want)]))
+
+
+# --- first block column in other memory layouts --------------------------------------------
+
+@pytest.mark.parametrize("s", [Shape(64, 7, 45, decay=None), Shape(45, 13, 31, decay=30.0), Shape(200, 5, 130)],
+                         ids=lambda s: f"Nt{s.Nt}_Nd{s.Nd}_Nm{s.Nm}")
+def test_setup_layouts(gpu, s):
+    """F given as [Nd][Nm][Nt], [Nm][Nd][Nt], [Nt][Nm][Nd] and a padded
+    [Nt][Nd][Nm] view: the setup transform reads the strides directly; the
+    stored spectrum equals the plain layout's bitwise, and the matvecs match
+    the oracle."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    F, m, d = make_F(s, 141), make_m(s, 142)[0], make_d(s, 143)[0]
+    Ft = torch.from_numpy(F).cuda()
+    base = Operator(Ft)
+    ref_spec = base.spectrum("d").cpu().numpy()
+    base.close()
+    pad = torch.full((s.Nt, s.Nd + 3, s.Nm + 5), float("nan"), dtype=torch.float64, device="cuda")
+    pad[:, : s.Nd, : s.Nm] = Ft
+    views = {
+        "dmt": Ft.permute(1, 2, 0).contiguous().permute(2, 0, 1),
+        "mdt": Ft.permute(2, 1, 0).contiguous().permute(2, 1, 0),
+        "tmd": Ft.permute(0, 2, 1).contiguous().permute(0, 2, 1),
+        "padded": pad[:, : s.Nd, : s.Nm],
+    }
+    mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
+    ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
+    for name, V in views.items():
+        _say("case layout", name, tuple(V.stride()))
+        assert not V.is_contiguous()
+        op = Operator(V)
+        assert np.array_equal(op.spectrum("d").cpu().numpy(), ref_spec), name
+        assert _rel(op.matvec(mt).cpu().numpy(), ref_d) <= FP64_TOL
+        assert _rel(op.rmatvec(dt).cpu().numpy(), ref_m) <= FP64_TOL
+        op.close()
+
+
+def test_setup_rejects_overlapping_strides(gpu):
+    import ctypes
+    import torch
+    from paper_2508_10202_amd import _lib
+    L = _lib.lib()
+    F = torch.zeros(64, dtype=torch.float64, device="cuda")
+    h = ctypes.c_void_p()
+    # (t, r, c) strides (4, 2, 1) with Nd = 3: rows overlap
+    assert L.ftm_setup_operator_strided(ctypes.byref(h), F.data_ptr(), 4, 3, 2, 4, 2, 1, None, None, 0, 1,
+                                        None) == _lib.ERR_INVALID
+    assert b"overlap" in L.ftm_last_error()
+
+
