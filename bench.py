@@ -179,6 +179,7 @@ def mixed_section(log, op, s, mt, dt, dout, mout, ref_d, ref_m, confs, reps=5):
 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6
 
 
 def multi_rhs_section(log):
@@ -223,14 +224,14 @@ def multi_rhs_section(log):
     p = timed(sep, reps=1)
     base_f, base_a = sum(p["fwd"]) * B, sum(p["adj"]) * B
     out["fp64_separate_ms"] = {"fwd": round(base_f, 3), "adj": round(base_a, 3)}
-    for prec, peak in (("ddsdd", PEAK_FP32_TFLOPS), ("dbbbd", PEAK_BF16_TFLOPS)):
+    for prec, peak, fbytes in (("ddsdd", PEAK_FP32_TFLOPS, 8), ("dbbbd", PEAK_BF16_TFLOPS, 4),
+                               ("ddddd", PEAK_FP64_TFLOPS, 16), ("ddsdd+a64", PEAK_FP64_TFLOPS, 8)):
         op.set_precision(fwd=prec, adj=prec)
         p = timed(lambda: (op.matvec(Mt, out=Yd), op.rmatvec(Dt, out=Ym)))
         e_f = oracle.relative_l2(Yd[pick].cpu().numpy(), ref_d)
         e_a = oracle.relative_l2(Ym[pick].cpu().numpy(), ref_m)
-        fbytes = 8 if prec[2] == "s" else 4
         gemm_bytes = s.K * s.Nd * s.Nm * fbytes + s.K * B * (s.Nm + s.Nd) * 8
-        rec = {}
+        rec = {"peak_tflops": peak}
         for name, kms, err, base in (("fwd", p["fwd"], e_f, base_f), ("adj", p["adj"], e_a, base_a)):
             t = kms[1] * 1e-3
             rec[name] = {"kernels_ms": [round(x, 4) for x in kms], "matvec_ms": round(sum(kms), 4),
@@ -239,7 +240,91 @@ def multi_rhs_section(log):
                          "speedup_vs_fp64_separate": round(base / sum(kms), 2)}
         out[prec] = rec
         log(f"multi-rhs {prec}: " + json.dumps(rec))
+    out["nrhs_sweep"] = {prec: nrhs_sweep(op, s, Mt, Dt, prec) for prec in ("ddsdd", "ddddd")}
+    log("multi-rhs nrhs sweep: " + json.dumps(out["nrhs_sweep"]))
+    out["hessian"] = hessian_section(log, op, F, s, "Nt=512 Nd=128 Nm=4096")
     op.close()
+    return out
+
+
+def nrhs_sweep(op, s, Mt, Dt, prec, counts=(1, 2, 4, 8, 16, 32, 64), reps=3):
+    """Time per matvec of nrhs right-hand sides, per direction, with the
+    automatic choice (the matrix-core GEMM from the crossover on) and with one
+    matrix-vector product per vector; ``auto_le_gemv`` says whether the
+    automatic choice was no slower (within 3%)."""
+    import torch
+    op.set_precision(fwd=prec, adj=prec)
+    dev = Mt.device
+    Yd = torch.empty((max(counts), s.Nt, s.Nd), dtype=torch.float64, device=dev)
+    Ym = torch.empty((max(counts), s.Nt, s.Nm), dtype=torch.float64, device=dev)
+    rows = []
+    for n in counts:
+        row = {"nrhs": n}
+        for mode in ("auto", "gemv"):
+            op.set_rhs_mode(mode)
+            ms = []
+            for fn, x, y in ((op.matvec, Mt, Yd), (op.rmatvec, Dt, Ym)):
+                fn(x[:n], out=y[:n])
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                for _ in range(reps):
+                    fn(x[:n], out=y[:n])
+                ev1.record()
+                torch.cuda.synchronize()
+                ms.append(round(ev0.elapsed_time(ev1) / reps, 4))
+            row[f"{mode}_ms"] = ms
+        row["auto_le_gemv"] = all(a <= 1.03 * g for a, g in zip(row["auto_ms"], row["gemv_ms"]))
+        rows.append(row)
+    op.set_rhs_mode("auto")
+    return rows
+
+
+def hessian_section(log, op, F, s, label, batch=64, full_prec="ddsdd", sample_prec="ddddd", sample_batches=8):
+    """Assembly of the dense data-space Hessian F F^T (identity prior, the
+    outer-loop workload of Section 3.2): all Nd * Nt actions on the unit
+    vectors, in batches through ftm_hessian_apply, at ``full_prec``; a timed
+    sample of ``sample_batches`` batches at ``sample_prec``.  Columns are
+    streamed through one output buffer (storing them is a pointer change).
+    One column is checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    dev = torch.device("cuda:0")
+    n_act = s.Nt * s.Nd
+    X = torch.zeros((batch, s.Nt, s.Nd), dtype=torch.float64, device=dev)
+    Y = torch.empty_like(X)
+    Xf = X.view(batch, -1)
+    ar = torch.arange(batch, device=dev)
+    out = {"workload": f"{label}: {n_act} actions F F^T e_j in batches of {batch}"}
+    for prec, nb in ((full_prec, (n_act + batch - 1) // batch), (sample_prec, sample_batches)):
+        op.set_precision(fwd=prec, adj=prec)
+        ws = torch.empty(((op.hessian_workspace_size(batch) + 7) // 8,), dtype=torch.float64, device=dev)
+        X.zero_()                                   # no unit entries left from the previous pass
+        op.hessian(X, workspace=ws, out=Y)          # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prev = None
+        for i in range(nb):
+            j = (i * batch + ar) % n_act
+            if prev is not None:
+                Xf[ar, prev] = 0.0
+            Xf[ar, j] = 1.0
+            prev = j
+            op.hessian(X, workspace=ws, out=Y)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # the last batch's first column against the oracle
+        jcol = int(prev[0])
+        e = np.zeros((s.Nt, s.Nd))
+        e.flat[jcol] = 1.0
+        err = oracle.relative_l2(Y[0].cpu().numpy(), oracle.hessian_data_space(F, e))
+        rec = {"actions": nb * batch, "seconds": round(dt, 3), "actions_per_s": round(nb * batch / dt, 1),
+               "ms_per_batch": round(dt / nb * 1e3, 3), "rel_err_sampled_column": float(f"{err:.3e}"),
+               "projected_full_assembly_s": round(n_act / (nb * batch / dt), 2)}
+        out[prec] = rec
+        log(f"hessian {label} {prec}: " + json.dumps(rec))
+        del ws
     return out
 
 
@@ -328,11 +413,11 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
                              for _ in range(2)]
     torch.cuda.synchronize()
     budget = 4 << 30
-    # output buffers: a ring of 8 per (operator, direction), 32 vectors each; a
+    # output buffers: a ring of 16 per (operator, direction), 32 vectors each; a
     # buffer is reused once the request that wrote it has completed (if it has
     # not, the client waits: that delay counts against the request's latency,
     # which is measured from its scheduled arrival)
-    ring = 8
+    ring = 16
     outs = {}
     for i, op in enumerate(ops):
         for adj in (0, 1):
@@ -471,7 +556,7 @@ def main() -> int:
     dev = torch.device("cuda:0")
     spectra = () if args.mixed == "none" else ("s", "h", "b")
     Ft = torch.from_numpy(F).to(dev)
-    op = Operator(Ft, spectra=spectra)
+    op = Operator(Ft, spectra=spectra, max_rhs=64)
     torch.cuda.synchronize()
     del Ft
     torch.cuda.empty_cache()
@@ -529,9 +614,28 @@ def main() -> int:
         cores = os.cpu_count()
     cpu_baseline = None
     if not args.no_cpu_baseline:
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+        except OSError:
+            pass
         cpu_baseline = {"value": 2.0 / (t4 - t2), "unit": "matvecs/s", "cores": int(cores), "kind": "oracle",
+                        "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
                         "sample": f"one forward ({t3 - t2:.2f}s) and one adjoint ({t4 - t3:.2f}s) float64 "
                                   "oracle matvec at Nt=1000, Nd=100, Nm=5000, whole vectors"}
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t5 = time.perf_counter()
+                oracle.forward(F, m)
+                t6 = time.perf_counter()
+            cpu_baseline["single_thread"] = {"value": 1.0 / (t6 - t5), "unit": "matvecs/s", "cores": 1,
+                                             "sample": f"one forward float64 oracle matvec at the same shape, "
+                                                       f"one thread ({t6 - t5:.2f}s)"}
+            log(f"cpu oracle, one thread: forward {t6 - t5:.2f}s")
+        except Exception as exc:  # threadpoolctl missing: report without the one-thread figure
+            log(f"no one-thread oracle timing: {exc}")
     rel = None if args.no_oracle else {"fwd": oracle.relative_l2(got_d, ref_d),
                                        "adj": oracle.relative_l2(got_m, ref_m)}
     if rel:
@@ -542,6 +646,18 @@ def main() -> int:
         confs = all_configs() if args.mixed == "all" else ds_configs() + HALF_CONFIGS
         mixed = mixed_section(log, op, s, mt, dt, dout, mout, ref_d, ref_m, confs)
 
+    paper_multi = None
+    if not args.no_multi_rhs:
+        # many right-hand sides and the data-space Hessian at the paper's shape
+        g = torch.Generator(device=dev)
+        g.manual_seed(2508_10202 + 100 * 2 + 3)
+        M64 = torch.randn((64, s.Nt, s.Nm), dtype=torch.float64, device=dev, generator=g)
+        D64 = torch.randn((64, s.Nt, s.Nd), dtype=torch.float64, device=dev, generator=g)
+        paper_multi = {"nrhs_sweep": {prec: nrhs_sweep(op, s, M64, D64, prec) for prec in ("ddsdd", "ddddd")}}
+        log("paper-shape nrhs sweep: " + json.dumps(paper_multi["nrhs_sweep"]))
+        del M64, D64
+        paper_multi["hessian"] = hessian_section(log, op, F, s, "Nt=1000 Nd=100 Nm=5000")
+        op.set_precision(fwd="ddddd", adj="ddddd")
     multi = None if args.no_multi_rhs else multi_rhs_section(log)
     sbg = None if args.no_multi_rhs else sbgemv_section(log)
     serving = None
@@ -565,7 +681,8 @@ def main() -> int:
         "hbm_gbs": {"fwd": round(matvec_bytes(s, 16) / (fwd_ms * 1e-3) / 1e9, 1),
                     "adj": round(matvec_bytes(s, 16) / (adj_ms * 1e-3) / 1e9, 1)},
         "kernels_ms": kms, "rel_err": rel, "roofline": roofline, "cpu_baseline": cpu_baseline,
-        "mixed": mixed, "multi_rhs": multi, "serving": serving, "sbgemv": sbg,
+        "mixed": mixed, "multi_rhs": multi, "paper_shape_multi_rhs": paper_multi, "serving": serving,
+        "sbgemv": sbg,
     }
     op.close()
     if args.copy_calibration_gib > 0:

@@ -224,6 +224,24 @@ ftm_status ftm_set_rhs_mode(ftm_operator op, int32_t mode);
  * direction for the current configuration). */
 ftm_status ftm_set_gemm_crossover(ftm_operator op, int64_t min_rhs);
 
+/* Tolerance-driven precision (Section 3.2: the fastest configuration whose
+ * error is within a tolerance set by the application, from the error-vs-time
+ * Pareto front).  For one direction, every {FP64, FP32, FP16, BF16}
+ * assignment to the five phases (and FP32 products with float64
+ * accumulation) whose product format's spectrum copy the operator keeps, and
+ * whose coarsest unit roundoff / 64 does not exceed the tolerance, runs on
+ * the probe input; its relative L2 error against the all-FP64 result on the
+ * same probe is measured, and those within the tolerance are timed (reps
+ * runs each, one vector).  The fastest (ties: the smaller error) becomes the
+ * direction's configuration; its error and time (ms) are returned.  The
+ * all-FP64 configuration always qualifies.
+ *   probe  device float64 [Nt][Nm] (forward) or [Nt][Nd] (adjoint): an input
+ *          representative of the application's (the errors depend on it).
+ * Needs the FP64 spectrum (the reference; FTM_ERR_UNSUPPORTED otherwise).
+ * Allocates scratch for the call; synchronises the stream. */
+ftm_status ftm_select_precision(ftm_operator op, int32_t adjoint, double tolerance, const double* probe, int32_t reps,
+                                ftm_precision* chosen, double* rel_err, double* ms, void* stream);
+
 /* Kernel and tile choices of one operator for its current precision
  * configuration (the entries are kept per direction and per storage or
  * compute format, so switching precision keeps each configuration's own).

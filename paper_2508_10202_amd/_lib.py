@@ -30,7 +30,7 @@ SCRATCH_BYTES = 96 << 20
 # Every symbol include/ftm.h declares.
 EXPORTS = ("ftm_setup_operator", "ftm_setup_operator_strided", "ftm_set_precision", "ftm_matvec", "ftm_rmatvec",
            "ftm_workspace_size", "ftm_apply", "ftm_apply_scratch",
-           "ftm_hessian_workspace_size", "ftm_hessian_apply", "ftm_round",
+           "ftm_hessian_workspace_size", "ftm_hessian_apply", "ftm_round", "ftm_select_precision",
            "ftm_get_spectrum", "ftm_operator_info", "ftm_profile_enable", "ftm_profile_read",
            "ftm_set_rhs_mode", "ftm_set_gemm_crossover", "ftm_autotune", "ftm_get_tuning",
            "ftm_set_tuning", "ftm_graph_create", "ftm_graph_launch", "ftm_graph_destroy",
@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
         "ftm_hessian_workspace_size": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "ftm_hessian_apply": [vp, vp, vp, i64, vp, ctypes.c_size_t, vp],
         "ftm_round": [i32, i32, vp, vp, i64, vp],
+        "ftm_select_precision": [vp, i32, ctypes.c_double, vp, i32, prec_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), vp],
         "ftm_get_spectrum": [vp, i32, i64, i64, vp, vp],
         "ftm_operator_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                               ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],

@@ -224,6 +224,33 @@ class Operator:
                                           _stream_ptr(stream)), "ftm_apply_scratch")
         return out[0] if single and out.dim() == 3 else out
 
+    def select_precision(self, tolerance: float, adjoint: bool = False, probe: torch.Tensor | None = None,
+                         reps: int = 3, stream=None) -> dict:
+        """Make the fastest configuration whose relative error (against the
+        all-FP64 result on ``probe``) is at most ``tolerance`` the direction's
+        configuration (``ftm_select_precision``).  Candidates use the spectrum
+        copies kept at setup.  ``probe`` defaults to a seeded N(0,1) input.
+        Returns ``{"prec": ..., "err": ..., "ms": ...}``."""
+        n_in = self.Nd if adjoint else self.Nm
+        if probe is None:
+            g = torch.Generator(device=self.device)
+            g.manual_seed(2508_10202)
+            probe = torch.randn((self.Nt, n_in), dtype=torch.float64, device=self.device, generator=g)
+        probe = _dev_f64(probe, "probe")
+        if probe.numel() != self.Nt * n_in:
+            raise ValueError("probe has the wrong size")
+        p, err, ms = FtmPrecision(), ctypes.c_double(), ctypes.c_double()
+        with torch.cuda.device(self.device):
+            check(lib().ftm_select_precision(self.handle, 1 if adjoint else 0, float(tolerance), probe.data_ptr(),
+                                             int(reps), ctypes.byref(p), ctypes.byref(err), ctypes.byref(ms),
+                                             _stream_ptr(stream)), "ftm_select_precision")
+        chosen = Precision(p.pad, p.fft, p.gemv, p.ifft, p.unpad, p.accum)
+        if adjoint:
+            self.adj = chosen
+        else:
+            self.fwd = chosen
+        return {"prec": str(chosen), "err": err.value, "ms": ms.value}
+
     def hessian_workspace_size(self, nrhs: int = 1) -> int:
         """Workspace bytes of one :meth:`hessian` call of ``nrhs`` vectors."""
         n = ctypes.c_size_t()

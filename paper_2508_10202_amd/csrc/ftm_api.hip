@@ -174,7 +174,6 @@ void release(ftm_operator op) {
   dev_free(&op->tw64i);
   dev_free(&op->tw32f);
   dev_free(&op->tw32i);
-  dev_free(&op->twg64);
   for (auto& s : op->spec) dev_free(&s);
   dev_free(&op->mhat);
   dev_free(&op->dhat);
@@ -203,12 +202,9 @@ std::vector<T> twiddle_table(const FftPlan& pl) {
 
 // Twiddle tables of the plans in their compute types.
 ftm_status upload_twiddles(ftm_operator op, hipStream_t st) {
-  const std::vector<double> t64f = twiddle_table<double>(op->plan_f), t64i = twiddle_table<double>(op->plan_i);
-  const std::vector<float> t32f = twiddle_table<float>(op->plan_f), t32i = twiddle_table<float>(op->plan_i);
-  const std::vector<double> tg64 = twiddle_table<double>(op->plan_g64);
+  const std::vector<double> t64f = twiddle_table<double>(op->plan_f64), t64i = twiddle_table<double>(op->plan_i64);
+  const std::vector<float> t32f = twiddle_table<float>(op->plan_f32), t32i = twiddle_table<float>(op->plan_i32);
   ftm_status s;
-  if ((s = dev_alloc(&op->twg64, tg64.size() * sizeof(double))) != FTM_OK) return s;
-  FTM_HIP(hipMemcpyAsync(op->twg64.p, tg64.data(), op->twg64.n, hipMemcpyHostToDevice, st));
   if ((s = dev_alloc(&op->tw64f, t64f.size() * sizeof(double))) != FTM_OK) return s;
   if ((s = dev_alloc(&op->tw64i, t64i.size() * sizeof(double))) != FTM_OK) return s;
   if ((s = dev_alloc(&op->tw32f, t32f.size() * sizeof(float))) != FTM_OK) return s;
@@ -457,8 +453,8 @@ ftm_status ftm_setup_operator_strided(ftm_operator* out, const double* F, int64_
     ftm_status s;
     if ((s = check_precision(pf)) != FTM_OK || (s = check_precision(pa)) != FTM_OK) return s;
 
-    FftPlan plan_f{}, plan_i{}, plan_g64{}, unused{};
-    if (!make_plans((int)L, 4, &plan_f, &plan_i) || !make_plans((int)L, 3, &plan_g64, &unused))
+    FftPlan plan_f64{}, plan_i64{}, plan_f32{}, plan_i32{};
+    if (!make_plans((int)L, 3, &plan_f64, &plan_i64) || !make_plans((int)L, 4, &plan_f32, &plan_i32))
       return fail(FTM_ERR_UNSUPPORTED, "no FFT plan for L = " + std::to_string(L));
 
     ftm_operator op = new ftm_operator_s();
@@ -470,9 +466,10 @@ ftm_status ftm_setup_operator_strided(ftm_operator* out, const double* F, int64_
     op->ldm = (int)((Nm + 7) / 8 * 8);
     op->ldd = (int)((Nd + 7) / 8 * 8);
     op->max_rhs = max_rhs;
-    op->plan_f = plan_f;
-    op->plan_i = plan_i;
-    op->plan_g64 = plan_g64;
+    op->plan_f64 = plan_f64;
+    op->plan_i64 = plan_i64;
+    op->plan_f32 = plan_f32;
+    op->plan_i32 = plan_i32;
     op->fwd = pf;
     op->adj = pa;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -972,6 +969,129 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
     }
   }
   return done(FTM_OK);
+}
+
+// Error model of a configuration, shaped after eq. (error) with unit
+// constants: the largest unit roundoff among its phases divided by 64 is a
+// floor below which no measured error of the configuration is expected.
+static double unit_roundoff(int dt) {
+  switch (dt) {
+    case DT_F32: return std::ldexp(1.0, -24);
+    case DT_F16: return std::ldexp(1.0, -11);
+    case DT_BF16: return std::ldexp(1.0, -8);
+    default: return std::ldexp(1.0, -53);
+  }
+}
+
+ftm_status ftm_select_precision(ftm_operator op, int32_t adjoint, double tolerance, const double* probe, int32_t reps,
+                                ftm_precision* chosen, double* rel_err, double* ms, void* stream) {
+  if (!op || !probe) return fail(FTM_ERR_INVALID, "operator or probe is NULL");
+  if (!(tolerance > 0.0)) return fail(FTM_ERR_INVALID, "tolerance must be > 0");
+  if (reps < 1 || reps > 1000) return fail(FTM_ERR_INVALID, "reps must be in [1, 1000]");
+  if (!op->spec[DT_F64].p)
+    return fail(FTM_ERR_UNSUPPORTED, "the float64 spectrum (the error reference) was not kept at setup");
+  const bool adj = adjoint != 0;
+  DeviceGuard g(op->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t ny = op->Nt * (adj ? op->Nm : op->Nd);
+  const ftm_precision kRef = {DT_F64, DT_F64, DT_F64, DT_F64, DT_F64, DT_F64};
+  size_t wmax = 0;
+  std::vector<ftm_precision> cand;
+  for (int code = 0; code < 1024; ++code) {
+    ftm_precision p;
+    int32_t* f[5] = {&p.pad, &p.fft, &p.gemv, &p.ifft, &p.unpad};
+    double umax = 0.0;
+    for (int i = 0, c = code; i < 5; ++i, c >>= 2) {
+      *f[i] = c & 3;
+      umax = std::max(umax, unit_roundoff(c & 3));
+    }
+    if (!op->spec[p.gemv].p) continue;            // its spectrum copy was not kept
+    if (code != 0 && umax / 64 > tolerance) continue;  // coarser than the tolerance allows
+    for (int acc = 0; acc < 2; ++acc) {
+      p.accum = acc == 0 ? (p.gemv == DT_F64 ? DT_F64 : DT_F32) : DT_F64;
+      if (acc == 1 && p.gemv != DT_F32) continue;  // float64 accumulation of FP32 storage only
+      cand.push_back(p);
+      wmax = std::max(wmax, op->workspace_bytes(1, adj, p));
+    }
+  }
+  DevBuf yref, y, ws, part;
+  constexpr int kBlocks = 256;
+  ftm_status s;
+  auto done = [&](ftm_status r) {
+    (void)hipStreamSynchronize(st);
+    dev_free(&yref);
+    dev_free(&y);
+    dev_free(&ws);
+    dev_free(&part);
+    return r;
+  };
+  if ((s = dev_alloc(&yref, ny * 8)) != FTM_OK || (s = dev_alloc(&y, ny * 8)) != FTM_OK ||
+      (s = dev_alloc(&ws, wmax)) != FTM_OK || (s = dev_alloc(&part, 2 * kBlocks * 8)) != FTM_OK)
+    return done(s);
+  ftm_rt::Exec base = op->exec(adj, 1, false);
+  base.use_gemm = false;
+  ftm_rt::MatvecIO io;
+  io.x = probe;
+  auto run = [&](const ftm_precision& p, double* out) -> ftm_status {
+    ftm_rt::Exec ex = base;
+    ex.p = p;
+    io.y = out;
+    return ftm_rt::run_matvec(op, adj, ex, io, 1, ftm_rt::carve_workspace(op, ws.p, 1, adj, p), st);
+  };
+  if ((s = run(kRef, reinterpret_cast<double*>(yref.p))) != FTM_OK) return done(s);
+  std::vector<double> host(2 * kBlocks);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return done(fail(FTM_ERR_HIP, "hipEventCreate"));
+  }
+  auto done_ev = [&](ftm_status r) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return done(r);
+  };
+  ftm_precision best = kRef;
+  double best_ms = 1e300, best_err = 0.0;
+  for (const ftm_precision& p : cand) {
+    // error against the float64 result on the probe
+    if ((s = run(p, reinterpret_cast<double*>(y.p))) != FTM_OK) return done_ev(s);
+    if (launch_sumsq_diff(reinterpret_cast<const double*>(y.p), reinterpret_cast<const double*>(yref.p), ny,
+                          reinterpret_cast<double*>(part.p), kBlocks, st) != hipSuccess)
+      return done_ev(fail(FTM_ERR_HIP, "error reduction launch"));
+    if (hipMemcpyAsync(host.data(), part.p, part.n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return done_ev(fail(FTM_ERR_HIP, "error reduction copy"));
+    double num = 0.0, den = 0.0;
+    for (int b = 0; b < kBlocks; ++b) {
+      num += host[2 * b];
+      den += host[2 * b + 1];
+    }
+    const double err = den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+    if (!(err <= tolerance)) continue;
+    // time the configurations within the tolerance
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i)
+      if ((s = run(p, reinterpret_cast<double*>(y.p))) != FTM_OK) return done_ev(s);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return done_ev(fail(FTM_ERR_HIP, "hipEventSynchronize"));
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    const double tm = (double)t / reps;
+    if (tm < best_ms || (tm == best_ms && err < best_err)) {
+      best_ms = tm;
+      best_err = err;
+      best = p;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(op->mu);
+    (adj ? op->adj : op->fwd) = best;
+  }
+  if (chosen) *chosen = best;
+  if (rel_err) *rel_err = best_err;
+  if (ms) *ms = best_ms;
+  return done_ev(FTM_OK);
 }
 
 ftm_status ftm_get_tuning(ftm_operator op, ftm_tuning* out) {

@@ -28,6 +28,8 @@
 // descending order and the inverse plan in ascending order, so the paired
 // passes take the smallest radix.  Twiddles come from the operator's per-pass
 // tables (long double on the host, rounded once).
+#include <type_traits>
+
 #include "ftm_device.h"
 #include "ftm_dft.h"
 #include "ftm_kernels.h"
@@ -477,28 +479,48 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
 
 // ---- the plans and workgroup shapes compiled for this length -------------------
 
+// Forward plans list the radices in descending order, inverse plans in
+// ascending order; float32 transforms take radices up to 16, float64 ones up
+// to 8 (a radix-16 float64 pass needs about 130 registers per thread).
 #if FTM_FIXED_N == 2000
-using PlanF = CPlan<16, 5, 5, 5>;
-using PlanI = CPlan<5, 5, 5, 16>;
+using PlanF32 = CPlan<16, 5, 5, 5>;
+using PlanI32 = CPlan<5, 5, 5, 16>;
+using PlanF64 = CPlan<5, 5, 5, 4, 4>;
+using PlanI64 = CPlan<4, 4, 5, 5, 5>;
 #elif FTM_FIXED_N == 1024
-using PlanF = CPlan<16, 8, 8>;
-using PlanI = CPlan<8, 8, 16>;
+using PlanF32 = CPlan<16, 8, 8>;
+using PlanI32 = CPlan<8, 8, 16>;
+using PlanF64 = CPlan<8, 8, 4, 4>;
+using PlanI64 = CPlan<4, 4, 8, 8>;
 #elif FTM_FIXED_N == 512
-using PlanF = CPlan<8, 8, 8>;
-using PlanI = CPlan<8, 8, 8>;
+using PlanF32 = CPlan<8, 8, 8>;
+using PlanI32 = CPlan<8, 8, 8>;
+using PlanF64 = CPlan<8, 8, 8>;
+using PlanI64 = CPlan<8, 8, 8>;
 #elif FTM_FIXED_N == 400
-using PlanF = CPlan<16, 5, 5>;
-using PlanI = CPlan<5, 5, 16>;
+using PlanF32 = CPlan<16, 5, 5>;
+using PlanI32 = CPlan<5, 5, 16>;
+using PlanF64 = CPlan<5, 5, 4, 4>;
+using PlanI64 = CPlan<4, 4, 5, 5>;
 #elif FTM_FIXED_N == 256
-using PlanF = CPlan<16, 16>;
-using PlanI = CPlan<16, 16>;
+using PlanF32 = CPlan<16, 16>;
+using PlanI32 = CPlan<16, 16>;
+using PlanF64 = CPlan<8, 8, 4>;
+using PlanI64 = CPlan<4, 8, 8>;
 #elif FTM_FIXED_N == 128
-using PlanF = CPlan<16, 8>;
-using PlanI = CPlan<8, 16>;
+using PlanF32 = CPlan<16, 8>;
+using PlanI32 = CPlan<8, 16>;
+using PlanF64 = CPlan<8, 4, 4>;
+using PlanI64 = CPlan<4, 4, 8>;
 #else
 #error "no fixed plan for this FTM_FIXED_N"
 #endif
-static_assert(PlanF::N == FTM_FIXED_N && PlanI::N == FTM_FIXED_N, "plan length");
+template <class TC>
+using PlanF = typename std::conditional<sizeof(TC) == 8, PlanF64, PlanF32>::type;
+template <class TC>
+using PlanI = typename std::conditional<sizeof(TC) == 8, PlanI64, PlanI32>::type;
+static_assert(PlanF32::N == FTM_FIXED_N && PlanI32::N == FTM_FIXED_N && PlanF64::N == FTM_FIXED_N &&
+                  PlanI64::N == FTM_FIXED_N, "plan length");
 
 // Threads per transform T (a power of two) and columns per tile C.  T gives
 // each thread 128 bytes of its transform's slab (8 float64 or 16 float32
@@ -540,13 +562,13 @@ hipError_t rfft_go(const RfftArgs& a, const void* tw, hipStream_t st) {
   const int64_t nwg = ntile * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
-  const size_t lds = (size_t)(C / 2) * slab_size<PlanF::N>() * sizeof(cplx<TC>);
+  const size_t lds = (size_t)(C / 2) * slab_size<FTM_FIXED_N>() * sizeof(cplx<TC>);
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
   if (is_half(a.r_pad) || is_half(a.r_fft) || is_half(a.r_next))
-    hipLaunchKernelGGL((rfft_fixed_kernel<PlanF, TC, TO, true, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a, t,
+    hipLaunchKernelGGL((rfft_fixed_kernel<PlanF<TC>, TC, TO, true, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a, t,
                        ntile);
   else
-    hipLaunchKernelGGL((rfft_fixed_kernel<PlanF, TC, TO, false, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
+    hipLaunchKernelGGL((rfft_fixed_kernel<PlanF<TC>, TC, TO, false, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
                        t, ntile);
   return hipGetLastError();
 }
@@ -558,13 +580,13 @@ hipError_t irfft_go(const IrfftArgs& a, const void* tw, hipStream_t st) {
   const int64_t nwg = ntile * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
-  const size_t lds = (size_t)(C / 2) * slab_size<PlanI::N>() * sizeof(cplx<TC>);
+  const size_t lds = (size_t)(C / 2) * slab_size<FTM_FIXED_N>() * sizeof(cplx<TC>);
   const cplx<TC>* t = reinterpret_cast<const cplx<TC>*>(tw);
   if (is_half(a.r_ifft) || is_half(a.r_unpad))
-    hipLaunchKernelGGL((irfft_fixed_kernel<PlanI, TI, TC, true, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
+    hipLaunchKernelGGL((irfft_fixed_kernel<PlanI<TC>, TI, TC, true, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
                        t, ntile);
   else
-    hipLaunchKernelGGL((irfft_fixed_kernel<PlanI, TI, TC, false, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
+    hipLaunchKernelGGL((irfft_fixed_kernel<PlanI<TC>, TI, TC, false, T, C>), dim3((unsigned)nwg), dim3(WG), lds, st, a,
                        t, ntile);
   return hipGetLastError();
 }
@@ -578,7 +600,7 @@ hipError_t irfft_go(const IrfftArgs& a, const void* tw, hipStream_t st) {
 // the operator's plan differs.  shape: 0 or 1 the default tile, 2 the smaller.
 bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
                                                 const void* tw, int shape, hipStream_t st, hipError_t* err) {
-  if (!same_plan<PlanF>(plan)) return false;
+  if (!(tc64 ? same_plan<PlanF64>(plan) : same_plan<PlanF32>(plan))) return false;
   const bool alt = shape == 2;
   if (tc64 && out64) *err = alt ? rfft_go<double, double, 2>(a, tw, st) : rfft_go<double, double, 1>(a, tw, st);
   else if (tc64) *err = alt ? rfft_go<double, float, 2>(a, tw, st) : rfft_go<double, float, 1>(a, tw, st);
@@ -588,7 +610,7 @@ bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, bool out64, const RfftA
 
 bool FTM_CAT(launch_irfft_fixed_, FTM_FIXED_N)(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan,
                                                  const void* tw, int shape, hipStream_t st, hipError_t* err) {
-  if (!same_plan<PlanI>(plan)) return false;
+  if (!(tc64 ? same_plan<PlanI64>(plan) : same_plan<PlanI32>(plan))) return false;
   const bool alt = shape == 2;
   if (tc64 && in64) *err = alt ? irfft_go<double, double, 2>(a, tw, st) : irfft_go<double, double, 1>(a, tw, st);
   else if (tc64) *err = alt ? irfft_go<float, double, 2>(a, tw, st) : irfft_go<float, double, 1>(a, tw, st);

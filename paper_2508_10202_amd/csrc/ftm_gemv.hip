@@ -384,6 +384,39 @@ hipError_t launch_round_values(int dt, bool from_f32, const double* x, double* y
   return hipGetLastError();
 }
 
+// Per-workgroup partial sums of (y - r)^2 and r^2 over n values, in a fixed
+// order (deterministic): partial[2 b], partial[2 b + 1] for workgroup b.
+__global__ void sumsq_diff_kernel(const double* __restrict__ y, const double* __restrict__ r, int64_t n,
+                                  double* __restrict__ partial) {
+  __shared__ double sd[256], sr[256];
+  double a = 0.0, c = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = y[i] - r[i];
+    a += d * d;
+    c += r[i] * r[i];
+  }
+  sd[threadIdx.x] = a;
+  sr[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sd[0];
+    partial[2 * blockIdx.x + 1] = sr[0];
+  }
+}
+
+hipError_t launch_sumsq_diff(const double* y, const double* r, int64_t n, double* partial, int nblocks,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(sumsq_diff_kernel, dim3(nblocks), dim3(256), 0, st, y, r, n, partial);
+  return hipGetLastError();
+}
+
 hipError_t launch_store_spectrum(const void* src, int dt, void* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(store_spectrum_kernel, grid_for(n), dim3(256), 0, st,
                      reinterpret_cast<const cplx<double>*>(src), dt, dst, n);

@@ -138,6 +138,10 @@ hipError_t launch_gemm_a64(bool adjoint, int fdt, bool in64, bool out64, const G
 // Round n float64 values into storage format dt as the kernels do (from
 // float32 after rounding to it, when from_f32).
 hipError_t launch_round_values(int dt, bool from_f32, const double* x, double* y, int64_t n, hipStream_t st);
+// Partial sums of (y - r)^2 and r^2 per workgroup (256 threads, nblocks
+// workgroups): partial[2 b], partial[2 b + 1].
+hipError_t launch_sumsq_diff(const double* y, const double* r, int64_t n, double* partial, int nblocks,
+                             hipStream_t st);
 // Round a float64 complex spectrum to storage format dt (n complex numbers).
 hipError_t launch_store_spectrum(const void* src, int dt, void* dst, int64_t n, hipStream_t st);
 // Widen rows x ncol complex numbers of storage format dt (row stride ld) to a

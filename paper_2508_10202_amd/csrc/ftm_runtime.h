@@ -57,19 +57,20 @@ struct ftm_operator_s {
   int ldm = 0, ldd = 0;  // padded column counts of spectra and workspaces
   int device = 0;
   int64_t max_rhs = 1;
-  // length-L plans: plan_f / plan_i for the fixed-plan forward (descending
-  // radices) and inverse (ascending) kernels, and in float32 for the
-  // runtime-plan kernels too; plan_g64 (radices up to 8) for the float64
-  // runtime-plan kernels.  Their per-pass twiddle tables in the compute types.
-  ftm::FftPlan plan_f{}, plan_i{}, plan_g64{};
-  ftm_rt::DevBuf tw64f, tw64i, tw32f, tw32i, twg64;
-  // the plans and tables of the input (forward) and output (inverse)
-  // transform for float64 (f64 = true) or float32 compute
+  // length-L plans of the forward (radices in descending order) and inverse
+  // (ascending) transforms, with radices up to 8 for float64 compute and up to
+  // 16 for float32 (the same radix sets as the fixed-plan kernels), and their
+  // per-pass twiddle tables in the compute types.  The runtime-plan kernels
+  // run the forward plans.
+  ftm::FftPlan plan_f64{}, plan_i64{}, plan_f32{}, plan_i32{};
+  ftm_rt::DevBuf tw64f, tw64i, tw32f, tw32i;
   ftm::FftPlans fft_in(bool f64) const {
-    return f64 ? ftm::FftPlans{&plan_f, tw64f.p, &plan_g64, twg64.p} : ftm::FftPlans{&plan_f, tw32f.p, &plan_f, tw32f.p};
+    return f64 ? ftm::FftPlans{&plan_f64, tw64f.p, &plan_f64, tw64f.p}
+               : ftm::FftPlans{&plan_f32, tw32f.p, &plan_f32, tw32f.p};
   }
   ftm::FftPlans fft_out(bool f64) const {
-    return f64 ? ftm::FftPlans{&plan_i, tw64i.p, &plan_g64, twg64.p} : ftm::FftPlans{&plan_i, tw32i.p, &plan_f, tw32f.p};
+    return f64 ? ftm::FftPlans{&plan_i64, tw64i.p, &plan_f64, tw64f.p}
+               : ftm::FftPlans{&plan_i32, tw32i.p, &plan_f32, tw32f.p};
   }
   ftm_rt::DevBuf spec[4];     // Fhat[K][Nd][ldm] per storage format
   ftm_rt::DevBuf mhat, dhat;  // the operator's own workspace, sized for max_rhs
@@ -92,7 +93,7 @@ struct ftm_operator_s {
   std::vector<hipEvent_t> event_pool;
 
   size_t bytes() const {
-    size_t b = tw64f.n + tw64i.n + tw32f.n + tw32i.n + twg64.n + mhat.n + dhat.n;
+    size_t b = tw64f.n + tw64i.n + tw32f.n + tw32i.n + mhat.n + dhat.n;
     for (const auto& s : spec) b += s.n;
     return b;
   }

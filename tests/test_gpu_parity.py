@@ -676,3 +676,28 @@ def test_setup_rejects_overlapping_strides(gpu):
     assert b"overlap" in L.ftm_last_error()
 
 
+
+# --- tolerance-driven precision --------------------------------------------------------
+
+@pytest.mark.parametrize("tol", [1e-12, 1e-6, 1e-3])
+def test_select_precision_meets_tolerance(gpu, tol):
+    """The library picks, per direction, the fastest configuration whose
+    measured error on the probe is within the tolerance: the chosen
+    configuration, run on another input, stays within it against the oracle
+    (with a factor 4 for the input change); at 1e-12 only float64 qualifies."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(200, 24, 1000)
+    F, m, d = make_F(s, 151), make_m(s, 152)[0], make_d(s, 153)[0]
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s", "h", "b"))
+    rf = op.select_precision(tol, adjoint=False, reps=2)
+    ra = op.select_precision(tol, adjoint=True, reps=2)
+    _say(f"case select {tol:g}: fwd {rf} adj {ra}")
+    assert rf["err"] <= tol and ra["err"] <= tol and rf["ms"] > 0 and ra["ms"] > 0
+    assert str(op.fwd) == rf["prec"] and str(op.adj) == ra["prec"]
+    if tol < 1e-9:
+        assert rf["prec"] == "ddddd" and ra["prec"] == "ddddd"
+    e_f = _rel(op.matvec(torch.from_numpy(m).cuda()).cpu().numpy(), oracle.forward(F, m))
+    e_a = _rel(op.rmatvec(torch.from_numpy(d).cuda()).cpu().numpy(), oracle.adjoint(F, d))
+    assert e_f <= 4 * tol and e_a <= 4 * tol
+    op.close()
