@@ -554,7 +554,9 @@ def main() -> int:
     m, d = m[0], d[0]
     log(f"inputs generated in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
-    spectra = () if args.mixed == "none" else ("s", "h", "b")
+    # the FP32 copy serves the multi-RHS sweep and the Hessian section; the
+    # half copies serve the mixed-precision sweep
+    spectra = (() if args.no_multi_rhs else ("s",)) if args.mixed == "none" else ("s", "h", "b")
     Ft = torch.from_numpy(F).to(dev)
     op = Operator(Ft, spectra=spectra, max_rhs=64)
     torch.cuda.synchronize()

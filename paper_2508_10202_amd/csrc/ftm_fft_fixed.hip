@@ -122,11 +122,17 @@ __device__ __forceinline__ void mid_passes(cplx<TC>* lds, int lane, const cplx<T
   }
 }
 
-// Which butterflies a paired unit u (0 <= u <= N/(2R)) of a pass with nb = N/R
-// butterflies holds: kind 0 butterfly 0 alone (the partner of its output q is
-// its output (R - q) mod R), kind 1 butterfly nb/2 alone (partner R-1-q),
-// kind 2 butterflies u and nb - u (partner R-1-q of the other one).
-__device__ __forceinline__ int unit_kind(int u, int nb) { return u == 0 ? 0 : (2 * u == nb ? 1 : 2); }
+// Paired passes (a pass with nb = N/R butterflies whose outputs or inputs are
+// needed in conjugate pairs) run in units u < (nb + 1) / 2: unit 0 holds
+// butterfly 0 (whose output q pairs with its own output (R - q) mod R) and,
+// for even nb, butterfly nb/2 (output q pairs with its own output R-1-q);
+// unit u > 0 holds butterflies u and nb - u (output q of each pairs with
+// output R-1-q of the other).  With nb/2 units for even nb, a pass fits T
+// threads exactly when the other passes do.
+template <int nb>
+__device__ __forceinline__ int partner_butterfly(int u) { return u == 0 ? nb / 2 : nb - u; }
+template <int nb>
+__device__ __forceinline__ bool has_second(int u) { return u != 0 || nb % 2 == 0; }
 
 // ---- phases 1+2: pad (+round) + real FFT -------------------------------------
 
@@ -171,13 +177,13 @@ __device__ __forceinline__ void sep_bin(cplx<TC>* lds, int k, cplx<TC> zk, cplx<
   lds[lds_ix(N / 2 + 1 + k)] = round_as<HALF>(round_as<HALF>(Y, r_fft), r_next);
 }
 
-// Last pass (Ns = nb, so jm = j) with butterflies j and nb - j in one thread;
-// the separated bins k <= N/2 of both series replace the transform in its
-// slab.  All reads precede all writes.
+// Last pass (Ns = nb, so jm = j) in paired units; the separated bins
+// k <= N/2 of both series replace the transform in its slab.  All reads
+// precede all writes.
 template <class P, int T, bool HALF, class TC>
 __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw, int r_fft,
                                           int r_next) {
-  constexpr int S = P::nst - 1, R = P::rad[S], N = P::N, nb = N / R, nu = nb / 2 + 1, hN = N / 2;
+  constexpr int S = P::nst - 1, R = P::rad[S], N = P::N, nb = N / R, nu = (nb + 1) / 2, hN = N / 2;
   constexpr int MU = (nu + T - 1) / T;
   const cplx<TC>* tws = tw + P::toff(S);
   cplx<TC> v1[MU][R], v2[MU][R];
@@ -185,11 +191,11 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
   for (int i = 0; i < MU; ++i) {
     const int u = lane + i * T;
     if (nu % T != 0 && u >= nu) continue;
-    const int j1 = u, j2 = nb - u;
+    const int j1 = u, j2 = partner_butterfly<nb>(u);
     v1[i][0] = lds[lds_ix(j1)];
 #pragma unroll
     for (int q = 1; q < R; ++q) v1[i][q] = cmul(lds[lds_ix(j1 + q * nb)], tws[j1 * R + q]);
-    if (unit_kind(u, nb) == 2) {
+    if (has_second<nb>(u)) {
       v2[i][0] = lds[lds_ix(j2)];
 #pragma unroll
       for (int q = 1; q < R; ++q) v2[i][q] = cmul(lds[lds_ix(j2 + q * nb)], tws[j2 * R + q]);
@@ -200,18 +206,19 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
   for (int i = 0; i < MU; ++i) {
     const int u = lane + i * T;
     if (nu % T != 0 && u >= nu) continue;
-    const int kind = unit_kind(u, nb), j1 = u, j2 = nb - u;
+    const int j1 = u, j2 = partner_butterfly<nb>(u);
     dft<R>(v1[i]);
-    if (kind == 0) {
+    if (has_second<nb>(u)) dft<R>(v2[i]);
+    if (u == 0) {
 #pragma unroll
       for (int q = 0; q < R; ++q)
         if (q * nb <= hN) sep_bin<HALF, N>(lds, q * nb, v1[i][q], v1[i][(R - q) % R], r_fft, r_next);
-    } else if (kind == 1) {
+      if constexpr (nb % 2 == 0) {
 #pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (j1 + q * nb <= hN) sep_bin<HALF, N>(lds, j1 + q * nb, v1[i][q], v1[i][R - 1 - q], r_fft, r_next);
+        for (int q = 0; q < R; ++q)
+          if (j2 + q * nb <= hN) sep_bin<HALF, N>(lds, j2 + q * nb, v2[i][q], v2[i][R - 1 - q], r_fft, r_next);
+      }
     } else {
-      dft<R>(v2[i]);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         if (j1 + q * nb <= hN) sep_bin<HALF, N>(lds, j1 + q * nb, v1[i][q], v2[i][R - 1 - q], r_fft, r_next);
@@ -222,9 +229,11 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
 }
 
 // Slab of transform `slot`: N + 2 complex values (the separated bins of both
-// series need N + 2), rounded up to 16.
+// series need N + 2), rounded up to 16, plus 2, so that consecutive slabs
+// start 4 (float) or 8 (float64) banks apart: the lanes of a tile load or
+// store walk across the slabs of one row and then meet distinct banks.
 template <int N>
-constexpr int slab_size() { return lds_size(N + 2); }
+constexpr int slab_size() { return lds_size(N + 2) + 2; }
 
 // A tile of C columns (C/2 transforms of T threads) per workgroup.
 template <class P, class TC, class TO, bool HALF, int T, int C>
@@ -257,7 +266,7 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
     }
     const double* xs = xb + off;
     TC* comp = reinterpret_cast<TC*>(slabs + (c / 2) * SL) + (c & 1);
-    constexpr int U = 4;  // loads in flight per thread
+    constexpr int U = 16;  // loads in flight per thread (a whole tile for most shapes)
     for (int t0 = t_first; t0 < Nt; t0 += U * t_step) {
       double v[U];
 #pragma unroll
@@ -320,42 +329,60 @@ __device__ __forceinline__ cplx<TC> conj_z_direct(cplx<TC> A, cplx<TC> B) { retu
 template <class TC>
 __device__ __forceinline__ cplx<TC> conj_z_mirror(cplx<TC> A, cplx<TC> B) { return {A.x + B.y, A.y - B.x}; }
 
-// First pass (Ns = 1, no twiddles) from the bins the tile load left in the
-// slab (series s at slot k, series s + 1 at slot N/2 + 1 + k), butterflies j
-// and nb - j paired so that each bin fills its own slot and its mirror's.
+// First pass (Ns = 1, no twiddles) in paired units, from the bins the tile
+// load left in the slab (series s at slot k, series s + 1 at slot
+// N/2 + 1 + k): each stored bin fills its own input slot and its mirror's.
 // All reads precede all writes.
 template <class P, int T, class TC>
 __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
-  constexpr int R = P::rad[0], N = P::N, nb = N / R, nu = nb / 2 + 1, hN = N / 2;
+  constexpr int R = P::rad[0], N = P::N, nb = N / R, nu = (nb + 1) / 2, hN = N / 2;
   constexpr int MU = (nu + T - 1) / T;
   cplx<TC> v1[MU][R], v2[MU][R];
 #pragma unroll
   for (int i = 0; i < MU; ++i) {
     const int u = lane + i * T;
     if (nu % T != 0 && u >= nu) continue;
-    const int kind = unit_kind(u, nb), j1 = u, j2 = nb - u;
+    const int j1 = u, j2 = partner_butterfly<nb>(u);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       v1[i][q] = {(TC)0, (TC)0};
       v2[i][q] = {(TC)0, (TC)0};
     }
+    if (u == 0) {
+      // butterfly 0: input q*nb, mirror (R - q)*nb
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int k = j1 + q * nb;
-      if (k <= hN) {
-        const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
-        v1[i][q] = conj_z_direct(A, B);
-        const cplx<TC> m = conj_z_mirror(A, B);
-        if (kind == 0) {
-          if (q != 0) v1[i][(R - q) % R] = m;
-        } else if (kind == 1) {
-          if (R - 1 - q != q) v1[i][R - 1 - q] = m;
-        } else {
-          v2[i][R - 1 - q] = m;
+      for (int q = 0; q < R; ++q) {
+        const int k = q * nb;
+        if (k <= hN) {
+          const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+          v1[i][q] = conj_z_direct(A, B);
+          if (q != 0) v1[i][(R - q) % R] = conj_z_mirror(A, B);
         }
       }
-    }
-    if (kind == 2) {
+      // butterfly nb/2: input nb/2 + q*nb, mirror nb/2 + (R-1-q)*nb
+      if constexpr (nb % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int k = j2 + q * nb;
+          if (k <= hN) {
+            const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+            v2[i][q] = conj_z_direct(A, B);
+            if (R - 1 - q != q) v2[i][R - 1 - q] = conj_z_mirror(A, B);
+          }
+        }
+      }
+    } else {
+      // butterflies u and nb - u: the mirror of input q of one is input
+      // R-1-q of the other
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int k = j1 + q * nb;
+        if (k <= hN) {
+          const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+          v1[i][q] = conj_z_direct(A, B);
+          v2[i][R - 1 - q] = conj_z_mirror(A, B);
+        }
+      }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int k = j2 + q * nb;
@@ -372,15 +399,15 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
   for (int i = 0; i < MU; ++i) {
     const int u = lane + i * T;
     if (nu % T != 0 && u >= nu) continue;
-    const int j1 = u, j2 = nb - u;
-    if (unit_kind(u, nb) == 2) {
+    const int j1 = u, j2 = partner_butterfly<nb>(u);
+    dft<R>(v1[i]);
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[lds_ix(j1 * R + q)] = v1[i][q];
+    if (has_second<nb>(u)) {
       dft<R>(v2[i]);
 #pragma unroll
       for (int q = 0; q < R; ++q) lds[lds_ix(j2 * R + q)] = v2[i][q];
     }
-    dft<R>(v1[i]);
-#pragma unroll
-    for (int q = 0; q < R; ++q) lds[lds_ix(j1 * R + q)] = v1[i][q];
   }
   tsync<T>();
 }
@@ -439,7 +466,7 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
     const cplx<TI>* in = reinterpret_cast<const cplx<TI>*>(a.in) + b * a.in_rhs_stride + (live ? s0 + c : 0);
     cplx<TC>* slab = slabs + (c / 2) * SL;
     const int off = (c & 1) ? hN + 1 : 0;
-    constexpr int U = 4;
+    constexpr int U = 16;
     for (int k0 = tid / C; k0 <= hN; k0 += U * ROWS) {
       cplx<TI> v[U];
 #pragma unroll
