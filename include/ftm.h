@@ -249,12 +249,21 @@ ftm_status ftm_select_precision(ftm_operator op, int32_t adjoint, double toleran
  *                     adjoint): 0 .. 3, 0 the default
  *   fft_shape[d][i]   transform kernel of direction d, i = 0 the input
  *                     transform (phases 1-2), 1 the output one (4-5): 0 the
- *                     default, 1 / 2 the fixed-plan kernels' larger / smaller
- *                     column tile (lengths that have them: 128, 256, 400,
- *                     512, 1024, 2000; others run the runtime-plan kernels
- *                     whatever the value), 3 the runtime-plan kernels
+ *                     default (the larger tile unless it gives fewer than 4
+ *                     tiles per CU, then the smaller), 1 / 2 the fixed-plan
+ *                     kernels' larger / smaller column tile (lengths that
+ *                     have them: 128, 256, 400, 512, 1024, 2000; others run
+ *                     the runtime-plan kernels whatever the value), 3 the
+ *                     runtime-plan kernels
  *   gemm_tile[d]      right-hand sides per matrix-core GEMM tile: 0 (the
  *                     default, 64), 16, 32 or 64
+ *   gemm_kind[d]      matrix-core instructions of an FP32-storage product with
+ *                     float32 accumulation: 1 the FP32 MFMA, 2 the BF16 MFMA
+ *                     on the three-term BF16 split of both operands (FP32
+ *                     accuracy, fewer cycles; faster when the product is
+ *                     compute bound), 0 the default (2 for the forward
+ *                     product at 64-right-hand-side tiles, else 1); other
+ *                     storage formats ignore it
  *   gemm_min_rhs[d]   smallest nrhs for which FTM_RHS_AUTO runs the GEMM (>= 2)
  *   ms[d]             the matvec time (milliseconds) of the last autotune at
  *                     these choices, 0 if none (read only) */
@@ -262,6 +271,7 @@ typedef struct ftm_tuning {
   int32_t gemv_variant[2];
   int32_t fft_shape[2][2];
   int32_t gemm_tile[2];
+  int32_t gemm_kind[2];
   int64_t gemm_min_rhs[2];
   double ms[2];
 } ftm_tuning;
@@ -270,10 +280,12 @@ typedef struct ftm_tuning {
  * points from measurements): for both directions at the operator's current
  * precision configuration, time the matrix-vector tile variants and the
  * transform kernels on one vector (reps timed runs each, scratch inputs) and
- * keep the fastest; then set the GEMM crossover to the smallest batch of 2,
- * 4, .., 32 right-hand sides for which the matrix-core product is no slower
- * than one matrix-vector product per vector (33 if none; this probe
- * allocates inputs and workspace for 32 vectors).  Synchronises the stream.  ftm_get_tuning /
+ * keep the fastest; for an FP32-storage product with float32 accumulation,
+ * keep the faster GEMM instructions (gemm_kind 1 or 2) at 64 right-hand
+ * sides; then set the GEMM crossover to the smallest batch of 2, 4, .., 32
+ * right-hand sides for which the matrix-core product is no slower than one
+ * matrix-vector product per vector (33 if none).  These probes allocate
+ * inputs and workspace for 64 vectors.  Synchronises the stream.  ftm_get_tuning /
  * ftm_set_tuning read and set the choice (for a persistent tuning cache kept
  * by the caller).  Out-of-range values are FTM_ERR_INVALID. */
 ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream);

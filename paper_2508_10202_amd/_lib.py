@@ -47,7 +47,8 @@ class FtmPrecision(ctypes.Structure):
 
 class FtmTuning(ctypes.Structure):
     _fields_ = [("gemv_variant", ctypes.c_int32 * 2), ("fft_shape", (ctypes.c_int32 * 2) * 2),
-                ("gemm_tile", ctypes.c_int32 * 2), ("gemm_min_rhs", ctypes.c_int64 * 2),
+                ("gemm_tile", ctypes.c_int32 * 2), ("gemm_kind", ctypes.c_int32 * 2),
+                ("gemm_min_rhs", ctypes.c_int64 * 2),
                 ("ms", ctypes.c_double * 2)]
 
 

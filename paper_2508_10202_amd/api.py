@@ -335,14 +335,16 @@ class Operator:
     def tuning(self) -> dict:
         """The kernel and tile choices for the current precision (``ftm_get_tuning``):
         per direction [forward, adjoint] the product's tile variant, the input
-        and output transforms' kernels, the GEMM tile, the GEMM crossover and
-        the autotuned matvec time."""
+        and output transforms' kernels, the GEMM tile, the FP32-storage GEMM
+        instructions, the GEMM crossover and the autotuned matvec time."""
         t = FtmTuning()
         check(lib().ftm_get_tuning(self.handle, ctypes.byref(t)), "ftm_get_tuning")
         return {"gemv_variant": list(t.gemv_variant), "fft_shape": [list(r) for r in t.fft_shape],
-                "gemm_tile": list(t.gemm_tile), "gemm_min_rhs": list(t.gemm_min_rhs), "ms": list(t.ms)}
+                "gemm_tile": list(t.gemm_tile), "gemm_kind": list(t.gemm_kind),
+                "gemm_min_rhs": list(t.gemm_min_rhs), "ms": list(t.ms)}
 
-    def set_tuning(self, gemv_variant=None, fft_shape=None, gemm_tile=None, gemm_min_rhs=None) -> None:
+    def set_tuning(self, gemv_variant=None, fft_shape=None, gemm_tile=None, gemm_min_rhs=None,
+                   gemm_kind=None) -> None:
         """Set some of the choices (``ftm_set_tuning``); each argument is a
         [forward, adjoint] pair (``fft_shape``: a pair of [input, output])."""
         t = FtmTuning()
@@ -354,6 +356,8 @@ class Operator:
                 t.fft_shape[d][0], t.fft_shape[d][1] = int(fft_shape[d][0]), int(fft_shape[d][1])
             if gemm_tile is not None:
                 t.gemm_tile[d] = int(gemm_tile[d])
+            if gemm_kind is not None:
+                t.gemm_kind[d] = int(gemm_kind[d])
             if gemm_min_rhs is not None:
                 t.gemm_min_rhs[d] = int(gemm_min_rhs[d])
         check(lib().ftm_set_tuning(self.handle, ctypes.byref(t)), "ftm_set_tuning")

@@ -59,6 +59,7 @@ ftm_rt::Exec ftm_operator_s::exec(bool adjoint, int64_t nrhs, bool allow_profile
   e.fft_shape_in = fft_shape[adjoint ? 1 : 0][0][e.p.fft == ftm::DT_F64 ? 1 : 0];
   e.fft_shape_out = fft_shape[adjoint ? 1 : 0][1][e.p.ifft == ftm::DT_F64 ? 1 : 0];
   e.gemm_tile = gemm_tile[adjoint ? 1 : 0][e.p.gemv];
+  e.gemm_kind = gemm_kind[adjoint ? 1 : 0];
   // many right-hand sides: one pass of the spectrum through the matrix cores
   // (float64 accumulation on the float64 ones, float32 on the others)
   const bool gemm_ok = nrhs >= 2;
@@ -328,6 +329,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ga.r_next = p.ifft;
   ga.variant = ex.gemv_variant;
   ga.rhs_tile = ex.gemm_tile;
+  ga.gemm_kind = ex.gemm_kind;
   const bool acc64 = p.accum == DT_F64;
   prof.mark(1);
   if (ex.use_gemm) {
@@ -896,17 +898,20 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
     best[dir] = b;
     best_t[dir] = bt;
   }
-  // GEMV <-> GEMM crossover per direction: the smallest batch of 2 .. 32
-  // right-hand sides for which the matrix-core product (at its default tile)
-  // is no slower than one matrix-vector product per vector (33: never up to 32)
-  constexpr int kMaxProbe = 32;
+  // The FP32-storage GEMM's instructions (float32 accumulation only): the
+  // faster of the FP32 MFMA and the split-term BF16 MFMA at 64 right-hand
+  // sides.  Then the GEMV <-> GEMM crossover per direction: the smallest
+  // batch of 2 .. 32 right-hand sides for which the matrix-core product (at
+  // its default tile) is no slower than one matrix-vector product per vector
+  // (33: never up to 32).
+  constexpr int kMaxProbe = 32, kKindProbe = 64;
   int64_t cross[2] = {2, 2};
   {
     DevBuf xb, yb, wb;
-    const size_t nbig = (size_t)kMaxProbe * nx * 8;
+    const size_t nbig = (size_t)kKindProbe * nx * 8;
     size_t wbytes = 0;
     for (int dir = 0; dir < 2; ++dir) {
-      const size_t w = op->workspace_bytes(kMaxProbe, dir == 1, best[dir].p);
+      const size_t w = op->workspace_bytes(kKindProbe, dir == 1, best[dir].p);
       wbytes = w > wbytes ? w : wbytes;
     }
     if ((s = dev_alloc(&xb, nbig)) != FTM_OK) return done(s);
@@ -926,6 +931,32 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
     ftm_rt::MatvecIO pio;
     pio.x = reinterpret_cast<const double*>(xb.p);
     pio.y = reinterpret_cast<double*>(yb.p);
+    auto time_batch = [&](int dir, const ftm_rt::Exec& ex, int n, double* ms) -> ftm_status {
+      const ftm_rt::Workspace pws = ftm_rt::carve_workspace(op, wb.p, n, dir == 1, ex.p);
+      ftm_status r = ftm_rt::run_matvec(op, dir == 1, ex, pio, n, pws, st);
+      if (r != FTM_OK) return r;
+      (void)hipEventRecord(e0, st);
+      for (int i = 0; i < reps; ++i) ftm_rt::run_matvec(op, dir == 1, ex, pio, n, pws, st);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(FTM_ERR_HIP, "hipEventSynchronize");
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      *ms = t;
+      return FTM_OK;
+    };
+    for (int dir = 0; dir < 2; ++dir) {
+      if (best[dir].p.gemv != DT_F32 || best[dir].p.accum == DT_F64) continue;
+      double tk[2] = {0.0, 0.0};
+      for (int kind = 1; kind <= 2; ++kind) {
+        ftm_rt::Exec ex = best[dir];
+        ex.use_gemm = true;
+        ex.gemm_tile = 0;
+        ex.gemm_kind = kind;
+        ftm_status r = time_batch(dir, ex, kKindProbe, &tk[kind - 1]);
+        if (r != FTM_OK) return release_probe(r);
+      }
+      best[dir].gemm_kind = tk[1] < tk[0] ? 2 : 1;
+    }
     for (int dir = 0; dir < 2; ++dir) {
       cross[dir] = kMaxProbe + 1;
       for (int n = 2; n <= kMaxProbe; n *= 2) {
@@ -934,16 +965,8 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
           ftm_rt::Exec ex = best[dir];
           ex.use_gemm = g == 0;
           ex.gemm_tile = 0;
-          const ftm_rt::Workspace pws = ftm_rt::carve_workspace(op, wb.p, n, dir == 1, ex.p);
-          ftm_status r = ftm_rt::run_matvec(op, dir == 1, ex, pio, n, pws, st);
+          ftm_status r = time_batch(dir, ex, n, g == 0 ? &t_gemm : &t_gemv);
           if (r != FTM_OK) return release_probe(r);
-          (void)hipEventRecord(e0, st);
-          for (int i = 0; i < reps; ++i) ftm_rt::run_matvec(op, dir == 1, ex, pio, n, pws, st);
-          (void)hipEventRecord(e1, st);
-          if (hipEventSynchronize(e1) != hipSuccess) return release_probe(fail(FTM_ERR_HIP, "hipEventSynchronize"));
-          float t = 0.f;
-          (void)hipEventElapsedTime(&t, e0, e1);
-          (g == 0 ? t_gemm : t_gemv) = t;
         }
         if (t_gemm <= t_gemv) {
           cross[dir] = n;
@@ -965,6 +988,7 @@ ftm_status ftm_autotune(ftm_operator op, int32_t reps, void* stream) {
       op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0] = best[dir].fft_shape_in;
       op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0] = best[dir].fft_shape_out;
       op->gemm_min_rhs[dir][p.gemv] = cross[dir];
+      op->gemm_kind[dir] = best[dir].gemm_kind;
       op->tuned_ms[dir] = best_t[dir];
     }
   }
@@ -1103,6 +1127,7 @@ ftm_status ftm_get_tuning(ftm_operator op, ftm_tuning* out) {
     out->fft_shape[dir][0] = op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0];
     out->fft_shape[dir][1] = op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0];
     out->gemm_tile[dir] = op->gemm_tile[dir][p.gemv];
+    out->gemm_kind[dir] = op->gemm_kind[dir];
     out->gemm_min_rhs[dir] = op->gemm_min_rhs[dir][p.gemv];
     out->ms[dir] = op->tuned_ms[dir];
   }
@@ -1119,6 +1144,7 @@ ftm_status ftm_set_tuning(ftm_operator op, const ftm_tuning* t) {
         return fail(FTM_ERR_INVALID, "fft_shape out of range");
     const int gt = t->gemm_tile[dir];
     if (gt != 0 && gt != 16 && gt != 32 && gt != 64) return fail(FTM_ERR_INVALID, "gemm_tile must be 0, 16, 32 or 64");
+    if (t->gemm_kind[dir] < 0 || t->gemm_kind[dir] > 2) return fail(FTM_ERR_INVALID, "gemm_kind must be 0, 1 or 2");
     if (t->gemm_min_rhs[dir] < 2) return fail(FTM_ERR_INVALID, "gemm_min_rhs must be >= 2");
   }
   std::lock_guard<std::mutex> lk(op->mu);
@@ -1128,6 +1154,7 @@ ftm_status ftm_set_tuning(ftm_operator op, const ftm_tuning* t) {
     op->fft_shape[dir][0][p.fft == DT_F64 ? 1 : 0] = t->fft_shape[dir][0];
     op->fft_shape[dir][1][p.ifft == DT_F64 ? 1 : 0] = t->fft_shape[dir][1];
     op->gemm_tile[dir][p.gemv] = t->gemm_tile[dir];
+    op->gemm_kind[dir] = t->gemm_kind[dir];
     op->gemm_min_rhs[dir][p.gemv] = t->gemm_min_rhs[dir];
   }
   return FTM_OK;

@@ -28,6 +28,7 @@
 // descending order and the inverse plan in ascending order, so the paired
 // passes take the smallest radix.  Twiddles come from the operator's per-pass
 // tables (long double on the host, rounded once).
+#include <algorithm>
 #include <type_traits>
 
 #include "ftm_device.h"
@@ -582,10 +583,17 @@ bool same_plan(const FftPlan& plan) {
 
 bool is_half(int dt) { return dt == DT_F16 || dt == DT_BF16; }
 
+// Whether the larger tile gives fewer than 4 tiles per CU (256 CUs).
+bool few_tiles(int64_t S, int nrhs, bool tc64) {
+  const int C = tc64 ? tile_columns<double>(1) : tile_columns<float>(1);
+  return (S + C - 1) / C * nrhs < 4 * 256;
+}
+
 template <class TC, class TO, int SH>
 hipError_t rfft_go(const RfftArgs& a, const void* tw, hipStream_t st) {
   constexpr int T = threads_per_transform<TC>(), C = tile_columns<TC>(SH), WG = C / 2 * T;
-  const int64_t ntile = (a.S + C - 1) / C;
+  // the tiles cover the padding columns S .. pad_to-1 too (written as zeros)
+  const int64_t ntile = (std::max(a.S, a.pad_to) + C - 1) / C;
   const int64_t nwg = ntile * a.nrhs;
   if (nwg <= 0) return hipSuccess;
   if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
@@ -624,11 +632,13 @@ hipError_t irfft_go(const IrfftArgs& a, const void* tw, hipStream_t st) {
 #define FTM_CAT(a, b) FTM_CAT2(a, b)
 
 // Forward transform with the plan compiled here; false (nothing launched) when
-// the operator's plan differs.  shape: 0 or 1 the default tile, 2 the smaller.
+// the operator's plan differs.  shape: 1 the larger tile, 2 the smaller, 0
+// the larger unless it gives fewer than 4 tiles per CU (the smaller tile then
+// spreads the transform over more workgroups; measured faster at such sizes).
 bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
                                                 const void* tw, int shape, hipStream_t st, hipError_t* err) {
   if (!(tc64 ? same_plan<PlanF64>(plan) : same_plan<PlanF32>(plan))) return false;
-  const bool alt = shape == 2;
+  const bool alt = shape == 2 || (shape == 0 && few_tiles(a.S, a.nrhs, tc64));
   if (tc64 && out64) *err = alt ? rfft_go<double, double, 2>(a, tw, st) : rfft_go<double, double, 1>(a, tw, st);
   else if (tc64) *err = alt ? rfft_go<double, float, 2>(a, tw, st) : rfft_go<double, float, 1>(a, tw, st);
   else *err = alt ? rfft_go<float, float, 2>(a, tw, st) : rfft_go<float, float, 1>(a, tw, st);
@@ -638,7 +648,7 @@ bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, bool out64, const RfftA
 bool FTM_CAT(launch_irfft_fixed_, FTM_FIXED_N)(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan,
                                                  const void* tw, int shape, hipStream_t st, hipError_t* err) {
   if (!(tc64 ? same_plan<PlanI64>(plan) : same_plan<PlanI32>(plan))) return false;
-  const bool alt = shape == 2;
+  const bool alt = shape == 2 || (shape == 0 && few_tiles(a.S, a.nrhs, tc64));
   if (tc64 && in64) *err = alt ? irfft_go<double, double, 2>(a, tw, st) : irfft_go<double, double, 1>(a, tw, st);
   else if (tc64) *err = alt ? irfft_go<float, double, 2>(a, tw, st) : irfft_go<float, double, 1>(a, tw, st);
   else *err = alt ? irfft_go<float, float, 2>(a, tw, st) : irfft_go<float, float, 1>(a, tw, st);

@@ -75,6 +75,42 @@ __device__ __forceinline__ void store_c(float* y, float re, float im, int r_gemv
 }
 
 // ---------------------------------------------------------------------------
+// FP32 products on the BF16 matrix cores.  An FP32 value splits exactly into
+// three BF16 terms x = x1 + x2 + x3: x1 keeps the top 8 significant bits
+// (the upper half of the word), x2 the next 8 of the residual, x3 the rest
+// (at most 8 bits); both subtractions are exact.  A product x y is the sum of
+// the eight terms xi yj other than x3 y3, which is below 2^-28 |x y|.  Every
+// term is exact in float32 and the MFMA accumulates in float32, so the result
+// has FP32 accuracy.  The eight 16x16x32 BF16 instructions take 128 cycles
+// where the 16x16x4 FP32 instructions doing the same multiply-adds take 256,
+// and the split costs four vector operations per value.
+// ---------------------------------------------------------------------------
+struct Split3 {
+  uint32_t h[3];  // BF16 bits of x1, x2, x3 (in the low half)
+};
+__device__ __forceinline__ Split3 split3(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const float r1 = x - __uint_as_float(u & 0xffff0000u);
+  const uint32_t v = __float_as_uint(r1);
+  const float r2 = r1 - __uint_as_float(v & 0xffff0000u);
+  return {{u >> 16, v >> 16, __float_as_uint(r2) >> 16}};
+}
+// pack two BF16 terms into one 32-bit word (lower k first)
+__device__ __forceinline__ uint32_t pack2(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
+
+// acc += sum of A_i B_j over all terms but A_3 B_3, smallest first
+__device__ __forceinline__ f32x4 mma_split(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // forward, FP32 storage: MFMA 16x16x4 f32
 // ---------------------------------------------------------------------------
 // NW waves per workgroup, 16 spectrum rows each.  Fewer waves per workgroup
@@ -85,6 +121,7 @@ __device__ __forceinline__ void store_c(float* y, float re, float im, int r_gemv
 #define FTM_GEMM_FWD_NW 4
 #endif
 constexpr int GEMM_FWD_NW = FTM_GEMM_FWD_NW;
+
 
 template <int NW, int TB>
 __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
@@ -264,6 +301,117 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
         const typename M::vec xa = *reinterpret_cast<const typename M::vec*>(&xs[16 * t + l16][32 * s + 8 * g]);
         re[t] = M::mma(xa, br, re[t]);
         im[t] = M::mma(xa, bi, im[t]);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int r = r0 + l16;
+  if (r >= a.Nd) return;
+  float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * g + v;
+      if (b < a.nrhs) {
+        float* y = Y + 2 * (b * a.y_rhs_stride + r);
+        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward, FP32 storage on the BF16 matrix cores (three-term split): the
+// tiling of the half-precision forward kernel; X' is staged in LDS as its
+// three BF16 terms, the spectrum values are split in registers.
+// ---------------------------------------------------------------------------
+template <int TB>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, int nbb, int nrb) {
+  constexpr int BM = 16 * TB;
+  __shared__ __align__(16) uint16_t xs[3][BM][KC + 8];  // X' terms, 64 reals per chunk
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * nrb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / nrb, rb = rem - bb * nrb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
+  const int kr = 2 * a.ld;
+
+  const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
+  const int64_t xrow = 2 * a.x_rhs_stride;
+  const float* __restrict__ Fk = reinterpret_cast<const float*>(a.F) + 2 * k * a.f_k_stride;
+  const int r_me = min(r0 + l16, a.Nd - 1);  // clamped rows: computed, never stored
+  const float* __restrict__ frow = Fk + (int64_t)r_me * kr;
+
+  f32x4 re[TB], im[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  // X' staging as in the half-precision kernel (16 threads read one row's
+  // 256 B); chunk kc + KC is loaded while the matrix cores work on chunk kc
+  int st_row[TB], st_col[TB];
+  const float* __restrict__ xsrc[TB];
+#pragma unroll
+  for (int q = 0; q < TB; ++q) {
+    const int e = threadIdx.x + GEMM_THREADS * q;
+    st_row[q] = e >> 4;
+    st_col[q] = (e & 15) * 4;
+    xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
+  }
+  float4 xv[TB];
+  uint4 fn[4];  // lane (l16, g): reals kc + 32 s + 8 g .. + 7 of its row, s = 0, 1
+  auto load_chunk = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < TB; ++q) {
+      const int col = kc + st_col[q];
+      xv[q] = col < kr ? *reinterpret_cast<const float4*>(xsrc[q] + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int col = kc + 32 * (h >> 1) + 8 * g + 4 * (h & 1);
+      fn[h] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  load_chunk(0);
+  for (int kc = 0; kc < kr; kc += KC) {
+#pragma unroll
+    for (int q = 0; q < TB; ++q) {
+      const float xq[4] = {xv[q].x, xv[q].y, xv[q].z, xv[q].w};
+      Split3 sp[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sp[e] = split3(xq[e]);
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        *reinterpret_cast<uint2*>(&xs[p][st_row[q]][st_col[q]]) =
+            make_uint2(pack2(sp[0].h[p], sp[1].h[p]), pack2(sp[2].h[p], sp[3].h[p]));
+    }
+    uint4 fv[4] = {fn[0], fn[1], fn[2], fn[3]};
+    __syncthreads();
+    if (kc + KC < kr) load_chunk(kc + KC);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      // the 8 reals of this lane: (re, im) pairs; Fr' = (re, -im), Fi' = (im, re)
+      const uint32_t u[8] = {fv[2 * s].x, fv[2 * s].y, fv[2 * s].z, fv[2 * s].w,
+                             fv[2 * s + 1].x, fv[2 * s + 1].y, fv[2 * s + 1].z, fv[2 * s + 1].w};
+      bf16x8 br[3], bi[3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const Split3 sre = split3(__uint_as_float(u[2 * q])), sim = split3(__uint_as_float(u[2 * q + 1]));
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          reinterpret_cast<uint32_t*>(&br[p])[q] = pack2(sre.h[p], sim.h[p] ^ 0x8000u);
+          reinterpret_cast<uint32_t*>(&bi[p])[q] = pack2(sim.h[p], sre.h[p]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        bf16x8 xa[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) xa[p] = *reinterpret_cast<const bf16x8*>(&xs[p][16 * t + l16][32 * s + 8 * g]);
+        re[t] = mma_split(xa, br, re[t]);
+        im[t] = mma_split(xa, bi, im[t]);
       }
     }
     __syncthreads();
@@ -484,6 +632,128 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
     }
 }
 
+// FP32 storage on the BF16 matrix cores (three-term split): the tiling of the
+// half-precision adjoint kernel, with the spectrum and data tiles staged in
+// LDS as their three BF16 terms.
+template <int TB>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_x3_kernel(GemvArgs a, int nbb, int ncb) {
+  constexpr int BM = 16 * TB, NX = BM * RC / GEMM_THREADS;  // data-tile loads per thread
+  __shared__ uint32_t fs[3][RC][ADJ_BN + 4];                // (re | im << 16) per complex and term
+  __shared__ __align__(16) uint16_t xr16[3][BM][RC + 8];
+  __shared__ __align__(16) uint16_t xi16[3][BM][RC + 8];
+  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
+  const int64_t per_k = (int64_t)nbb * ncb;
+  const int64_t k = wg / per_k;
+  const int rem = (int)(wg - k * per_k);
+  const int bb = rem / ncb, cb = rem - bb * ncb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int b0 = bb * BM, c0 = cb * ADJ_BN;
+
+  const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
+  const cplx<float>* __restrict__ Fk = reinterpret_cast<const cplx<float>*>(a.F) + k * a.f_k_stride;
+
+  f32x4 re[TB], im[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
+  // on chunk r0: the spectrum tile (32 rows x 64 columns, two complex per
+  // 16-byte load) and the data tile (BM right-hand sides x 32 sensors).
+  float4 fv[4];
+  cplx<float> xv[NX];
+  auto load_chunk = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx >> 5, col = (idx & 31) * 2;
+      const int r = r0 + row, c = c0 + col;
+      fv[q] = (r < a.Nd && c < a.ld) ? __builtin_bit_cast(float4, load_stream(Fk + (int64_t)r * a.ld + c))
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int bl = idx >> 5, rr = idx & 31;
+      const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
+      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+    }
+  };
+  load_chunk(0);
+  for (int r0 = 0; r0 < a.Nd; r0 += RC) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int row = idx >> 5, col = (idx & 31) * 2;
+      const Split3 s0r = split3(fv[q].x), s0i = split3(fv[q].y), s1r = split3(fv[q].z), s1i = split3(fv[q].w);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        fs[p][row][col] = pack2(s0r.h[p], s0i.h[p]);
+        fs[p][row][col + 1] = pack2(s1r.h[p], s1i.h[p]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      const int bl = idx >> 5, rr = idx & 31;
+      const Split3 sr = split3(xv[q].x), si = split3(xv[q].y);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        xr16[p][bl][rr] = (uint16_t)sr.h[p];
+        xi16[p][bl][rr] = (uint16_t)si.h[p];
+      }
+    }
+    __syncthreads();
+    if (r0 + RC < a.Nd) load_chunk(r0 + RC);
+    // B operands: the terms of fr and fi of sensors 8 g .. 8 g + 7 at this
+    // lane's column
+    bf16x8 fr[3], fi[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint4 ufr, ufi;
+      uint32_t* pr = reinterpret_cast<uint32_t*>(&ufr);
+      uint32_t* pi = reinterpret_cast<uint32_t*>(&ufi);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t w0 = fs[p][8 * g + 2 * q][w * 16 + l16], w1 = fs[p][8 * g + 2 * q + 1][w * 16 + l16];
+        pr[q] = (w0 & 0xffffu) | (w1 << 16);
+        pi[q] = (w0 >> 16) | (w1 & 0xffff0000u);
+      }
+      fr[p] = __builtin_bit_cast(bf16x8, ufr);
+      fi[p] = __builtin_bit_cast(bf16x8, ufi);
+    }
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      bf16x8 vxr[3], vxi[3], vxn[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const uint4 uxr = *reinterpret_cast<const uint4*>(&xr16[p][16 * t + l16][8 * g]);
+        const uint4 uxi = *reinterpret_cast<const uint4*>(&xi16[p][16 * t + l16][8 * g]);
+        const uint4 uxn = make_uint4(uxr.x ^ 0x80008000u, uxr.y ^ 0x80008000u, uxr.z ^ 0x80008000u,
+                                     uxr.w ^ 0x80008000u);
+        vxr[p] = __builtin_bit_cast(bf16x8, uxr);
+        vxi[p] = __builtin_bit_cast(bf16x8, uxi);
+        vxn[p] = __builtin_bit_cast(bf16x8, uxn);
+      }
+      re[t] = mma_split(vxr, fr, re[t]);
+      re[t] = mma_split(vxi, fi, re[t]);
+      im[t] = mma_split(vxi, fr, im[t]);
+      im[t] = mma_split(vxn, fi, im[t]);
+    }
+    __syncthreads();
+  }
+
+  const int c = c0 + w * 16 + l16;
+  if (c >= a.Nm) return;
+  float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+#pragma unroll
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * g + v;
+      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // float64 accumulation: MFMA 16x16x4 f64, from float64 storage (an all-FP64
 // product) or FP32 storage (FP32 values, products exact in float64; the
@@ -679,7 +949,11 @@ static int rhs_tile(const GemvArgs& a) {
 template <int TB>
 static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
   const int nbb = (a.nrhs + 16 * TB - 1) / (16 * TB);
-  if (fdt == DT_F32) {
+  // FP32 storage: the split-term BF16 kernel by default only at 64-RHS tiles,
+  // where the product is compute bound (measured faster there, slower on
+  // memory-bound smaller tiles)
+  const bool split = a.gemm_kind == 2 || (a.gemm_kind == 0 && TB == 4);
+  if (fdt == DT_F32 && !split) {
     const int nrb = (a.Nd + 16 * GEMM_FWD_NW - 1) / (16 * GEMM_FWD_NW);
     const int64_t nwg = (int64_t)a.K * nbb * nrb;
     if (nwg <= 0) return hipSuccess;
@@ -692,6 +966,7 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
+    case DT_F32: hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB>), grid, block, 0, st, a, nbb, nrb); break;
     case DT_F16: hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, nrb); break;
     case DT_BF16: hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, nrb); break;
     default: return hipErrorInvalidValue;
@@ -706,7 +981,10 @@ static hipError_t gemm_adj_go(int fdt, const GemvArgs& a, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
-    case DT_F32: hipLaunchKernelGGL((gemm_adj_f32_kernel<TB>), grid, block, 0, st, a, nbb, ncb); break;
+    case DT_F32:  // the split-term kernel only when asked for (kind 2)
+      if (a.gemm_kind == 2) hipLaunchKernelGGL((gemm_adj_x3_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
+      else hipLaunchKernelGGL((gemm_adj_f32_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
+      break;
     case DT_F16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, ncb); break;
     case DT_BF16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, ncb); break;
     default: return hipErrorInvalidValue;

@@ -15,8 +15,9 @@ constexpr int MAX_STAGES = 16;
 #endif
 constexpr int FFT_POINTS = FTM_FFT_POINTS;
 // FFT kernel choices (for the autotuner): 0 the default (the fixed-plan
-// kernels where the length has them, shape 1), 1 and 2 the fixed-plan kernels'
-// two workgroup shapes, 3 the runtime-plan kernels.
+// kernels where the length has them, with the larger tile unless it gives
+// fewer than 4 tiles per CU), 1 and 2 the fixed-plan kernels' larger and
+// smaller column tiles, 3 the runtime-plan kernels.
 constexpr int FFT_SHAPES = 4;
 constexpr int FFT_SHAPE_GENERIC = 3;
 // Whether length N has fixed-plan kernels.
@@ -106,6 +107,7 @@ struct GemvArgs {
   int r_gemv, r_next;
   int variant;   // kernel variant (tile shape), 0 = default; see ftm_gemv.hip
   int rhs_tile;  // right-hand sides per GEMM tile: 16, 32 or 64 (0: by nrhs)
+  int gemm_kind; // FP32-storage GEMM: 1 FP32 MFMA, 2 BF16 MFMA on split terms, 0 default
 };
 
 // Number of tile-shape variants of the matrix-vector kernels.

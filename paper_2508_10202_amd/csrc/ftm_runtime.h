@@ -46,6 +46,7 @@ struct Exec {
   int gemv_variant = 0;
   int fft_shape_in = 0, fft_shape_out = 0;  // kernels of the two transforms (0 = default)
   int gemm_tile = 0;                         // right-hand sides per GEMM tile (0 = default)
+  int gemm_kind = 0;                         // FP32-storage GEMM instructions (0 = default)
   bool use_gemm = false;
   bool profile = false;  // record HIP events around the kernels
 };
@@ -82,6 +83,7 @@ struct ftm_operator_s {
   int64_t gemm_min_rhs[2][4] = {{2, 2, 2, 2}, {2, 2, 2, 2}};  // [direction][storage format] crossover
   int variant[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};          // [direction][storage format] tile variant
   int gemm_tile[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};        // [direction][storage format] GEMM tile
+  int gemm_kind[2] = {0, 0};                                  // [direction] FP32-storage GEMM instructions
   int fft_shape[2][2][2] = {};  // [direction][input / output transform][float64 compute] transform kernel
   double tuned_ms[2] = {0.0, 0.0};
   bool profiling = false;

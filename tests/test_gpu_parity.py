@@ -206,6 +206,35 @@ def test_multi_rhs_matches_single_bitwise(gpu):
     op.close()
 
 
+@pytest.mark.parametrize("shape", [1, 2, 3])
+def test_fft_tiles_zero_the_padding_columns(gpu, shape):
+    """Every transform kernel writes the workspace columns between Nm (and Nd)
+    and their padded widths as zeros: with Nm = 4 mod 8 and Nd = 4 mod 8 the
+    smaller column tile ends exactly at Nm, and a NaN-filled caller workspace
+    must still give the oracle's result."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(64, 20, 500)
+    F, M, D = make_F(s, 61), make_m(s, 62, nrhs=3), make_d(s, 63, nrhs=3)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s",), max_rhs=3)
+    Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
+    want_d = np.stack([oracle.forward(F, M[b]) for b in range(3)])
+    want_m = np.stack([oracle.adjoint(F, D[b]) for b in range(3)])
+    for prec in ("ddddd", "sssss"):
+        op.set_precision(fwd=prec, adj=prec)
+        op.set_tuning(fft_shape=((shape, shape), (shape, shape)))
+        nb = max(op.workspace_size(3, adjoint=a) for a in (False, True))
+        ws = torch.full((nb // 8 + 1,), float("nan"), dtype=torch.float64, device="cuda")
+        yd = op.apply(Mt, ws).cpu().numpy()
+        ws.fill_(float("nan"))
+        ym = op.apply(Dt, ws, adjoint=True).cpu().numpy()
+        tol = 1e-12 if prec == "ddddd" else 1e-5
+        assert np.isfinite(yd).all() and np.isfinite(ym).all(), (prec, shape)
+        assert oracle.relative_l2(yd, want_d) < tol, (prec, shape)
+        assert oracle.relative_l2(ym, want_m) < tol, (prec, shape)
+    op.close()
+
+
 def test_apply_on_caller_workspaces_concurrently(gpu):
     """ftm_apply on two NaN-filled caller workspaces, on two streams at once:
     both results equal the operator's own-workspace call bitwise."""
@@ -417,16 +446,20 @@ def test_gemm_path_vs_oracle(gpu, gemm_case, prec, nrhs):
     op.set_rhs_mode("gemm")
     lo_f, hi_f = _gemm_bounds(prec, s.L, s.Nm)
     lo_a, hi_a = _gemm_bounds(prec, s.L, s.Nd)
+    # FP32-storage products with float32 accumulation: both instruction kinds
+    kinds = (0, 1, 2) if prec[2] == "s" and "+a64" not in prec else (0,)
     for tile in (0, 16, 32, 64):
-        _say("case gemm", prec, nrhs, "tile", tile)
-        op.set_tuning(gemm_tile=(tile, tile))
-        gd, gm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
-        e_f, e_a = _rel(gd, ref_d[:nrhs]), _rel(gm, ref_m[:nrhs])
-        _say(f"  gemm {prec} nrhs={nrhs} tile={tile}: fwd {e_f:.3e} adj {e_a:.3e}; gemv fwd {_rel(vd, ref_d[:nrhs]):.3e}")
-        assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
-        for b in range(nrhs):                 # every right-hand side, not just the norm
-            assert _rel(gd[b], ref_d[b]) <= hi_f and _rel(gm[b], ref_m[b]) <= hi_a
-        assert _rel(gd, vd) <= 2 * hi_f and _rel(gm, vm) <= 2 * hi_a
+        for kind in kinds:
+            _say("case gemm", prec, nrhs, "tile", tile, "kind", kind)
+            op.set_tuning(gemm_tile=(tile, tile), gemm_kind=(kind, kind))
+            gd, gm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
+            e_f, e_a = _rel(gd, ref_d[:nrhs]), _rel(gm, ref_m[:nrhs])
+            _say(f"  gemm {prec} nrhs={nrhs} tile={tile} kind={kind}: fwd {e_f:.3e} adj {e_a:.3e}; "
+                 f"gemv fwd {_rel(vd, ref_d[:nrhs]):.3e}")
+            assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a
+            for b in range(nrhs):                 # every right-hand side, not just the norm
+                assert _rel(gd[b], ref_d[b]) <= hi_f and _rel(gm[b], ref_m[b]) <= hi_a
+            assert _rel(gd, vd) <= 2 * hi_f and _rel(gm, vm) <= 2 * hi_a
     op.close()
 
 
@@ -441,9 +474,10 @@ def test_gemm_multi_rhs_shape(gpu):
     ref_d, ref_m = oracle.forward(F, M[pick]), oracle.adjoint(F, D[pick])
     op = Operator(torch.from_numpy(F).cuda(), fwd="ddsdd", adj="ddsdd", spectra=("b", "d"), max_rhs=64)
     Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
-    for prec in ("ddsdd", "dbbbd", "ddddd", "ddsdd+a64"):
-        _say("case multi-rhs", prec)
+    for prec, kind in (("ddsdd", 1), ("ddsdd", 2), ("dbbbd", 0), ("ddddd", 0), ("ddsdd+a64", 0)):
+        _say("case multi-rhs", prec, "kind", kind)
         op.set_precision(fwd=prec, adj=prec)
+        op.set_tuning(gemm_kind=(kind, kind))
         gd, gm = op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy()
         e_f, e_a = _rel(gd[pick], ref_d), _rel(gm[pick], ref_m)
         lo_f, hi_f = _gemm_bounds(prec, s.L, s.Nm)
@@ -541,6 +575,7 @@ def test_autotune_keeps_results_and_caches(gpu, tmp_path):
         assert all(0 <= v <= FFT_GENERIC for r in rec["fft_shape"] for v in r)
         assert all(t > 0 for t in rec["ms"])
         assert all(2 <= c <= 33 for c in rec["gemm_min_rhs"])
+        assert all(k in (0, 1, 2) for k in rec["gemm_kind"])
         assert op.autotune(cache=cache)["cached"]
         mt, dt = torch.from_numpy(m).cuda(), torch.from_numpy(d).cuda()
         ref_d, ref_m = oracle.forward(F, m), oracle.adjoint(F, d)
@@ -561,6 +596,8 @@ def test_autotune_keeps_results_and_caches(gpu, tmp_path):
             op.set_tuning(gemv_variant=(4, 0))
         with pytest.raises(FtmError):
             op.set_tuning(fft_shape=((4, 0), (0, 0)))
+        with pytest.raises(FtmError):
+            op.set_tuning(gemm_kind=(3, 0))
         op.close()
 
 
