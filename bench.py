@@ -381,13 +381,17 @@ def sbgemv_section(log):
     return rows
 
 
-def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000.0):
+def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000.0, budget_gib: float = 4.0):
     """Poisson arrivals at `rate` req/s against 4 device-resident FP32
     operators; each request is forward or adjoint (50/50) with 1..32 vectors,
-    operator uniform.  Workspace budget 4 GiB (it binds: a 32-vector request
-    on the largest operators needs 1.3-2.1 GB).  A second, shorter run offers
-    the same mix at 3/4 of the throughput the first one reached
-    (`below_capacity`), where the latency is not dominated by queueing."""
+    operator uniform.  Workspace budget `budget_gib` (at 4 GiB it binds: a
+    32-vector request on the largest operators needs 1.3-2.1 GB).  A second,
+    shorter run offers the same mix at 3/4 of the throughput the first one
+    reached (`below_capacity`), where the latency is not dominated by
+    queueing.  `capacity` is what the GPU can serve with one batch at a time:
+    each operator and direction timed alone on 16 vectors (about one mean
+    request) and on 64 (a full coalesced batch), averaged over the uniform
+    mix of operators and directions."""
     import numpy as np
     import torch
 
@@ -412,7 +416,34 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
             pools[i, adj] = [torch.randn((32, op.Nt, n), dtype=torch.float64, device=dev, generator=g)
                              for _ in range(2)]
     torch.cuda.synchronize()
-    budget = 4 << 30
+    # serial capacity: ms per batch of 16 and of 64 vectors, per (operator, direction)
+    cap = {}
+    wsb = max(op.workspace_size(64, adjoint=bool(a)) for op in ops for a in (0, 1))
+    cws = torch.empty(((wsb + 7) // 8,), dtype=torch.float64, device=dev)
+    for i, op in enumerate(ops):
+        for adj in (0, 1):
+            n = op.Nd if adj else op.Nm
+            xin = torch.randn((64, op.Nt, n), dtype=torch.float64, device=dev, generator=g)
+            yout = torch.empty((64, op.Nt, op.Nm if adj else op.Nd), dtype=torch.float64, device=dev)
+            for nb in (16, 64):
+                def fn():
+                    op.apply(xin[:nb], cws, adjoint=bool(adj), out=yout[:nb])
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    fn()
+                torch.cuda.synchronize()
+                cap[i, adj, nb] = (time.perf_counter() - t0) / 5 * 1e3
+            del xin, yout
+    del cws
+    mean_vec = 16.5                                   # mean of 1..32 vectors per request
+    ms16 = float(np.mean([cap[i, a, 16] for i in range(len(ops)) for a in (0, 1)])) * mean_vec / 16
+    ms64 = float(np.mean([cap[i, a, 64] for i in range(len(ops)) for a in (0, 1)])) * mean_vec / 64
+    capacity = {"ms_per_batch": {f"op{i}_{'adj' if a else 'fwd'}_{nb}": round(v, 3) for (i, a, nb), v in cap.items()},
+                "req_s_at_16_vector_batches": round(1e3 / ms16, 1), "req_s_at_64_vector_batches": round(1e3 / ms64, 1)}
+    log("serving capacity: " + json.dumps({k: v for k, v in capacity.items() if k != "ms_per_batch"}))
+    budget = int(budget_gib * (1 << 30)) // 256 * 256
     # output buffers: a ring of 16 per (operator, direction), 32 vectors each; a
     # buffer is reused once the request that wrote it has completed (if it has
     # not, the client waits: that delay counts against the request's latency,
@@ -479,7 +510,7 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
                "vectors_s": round(vec / max(t_end - warmup, 1e-9), 1),
                "offered_req_s": round(rate, 1), "wall_s": round(t_end, 2),
                "max_submit_lag_ms": round(float(lag.max() * 1e3), 3),
-               "workspace_budget_bytes": budget, "stats": st}
+               "workspace_budget_bytes": budget, "capacity": capacity, "stats": st}
         return rec, srv, keep
 
     out, srv, keep = run(rate, seconds, 4, True)
@@ -527,6 +558,8 @@ def main() -> int:
                     help="skip the 64-right-hand-side GEMM measurement (Nt=512, Nd=128, Nm=4096)")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="measured duration of the serving run (after a 1 s warm-up); 0 skips it")
+    ap.add_argument("--serving-budget-gib", type=float, default=4.0,
+                    help="workspace budget of the serving run's server")
     ap.add_argument("--json-out", default=None, help="also write the full record here")
     args = ap.parse_args()
     if args.no_oracle:
@@ -665,7 +698,7 @@ def main() -> int:
     serving = None
     if args.serving_seconds > 0:
         op.close()
-        serving = serving_section(log, args.serving_seconds)
+        serving = serving_section(log, args.serving_seconds, budget_gib=args.serving_budget_gib)
 
     achieved = gb_fwd
     roofline = {"bound": "hbm", "kernel": "gemv_fwd_kernel<s_f64,double,double,double> (phase 3, float64)",
