@@ -42,11 +42,27 @@
 namespace ftm {
 namespace {
 
-// LDS slot of complex element i of a slab: the XOR of the low 4 bits with the
-// 16-element group index spreads the strided writes of the early passes over
-// the banks; it permutes each group of 16, so a slab is N rounded up to 16.
-__device__ __forceinline__ int lds_ix(int i) { return i ^ ((i >> 4) & 15); }
-constexpr int lds_size(int n) { return (n + 15) / 16 * 16; }
+// LDS slot of complex element i of a slab: one unused slot after every 16
+// elements spreads the strided accesses of the passes over the banks (lanes
+// j writing j R + q, R = 16, meet 17 j + q, distinct banks), and for strides
+// that are multiples of 16 the slots of a butterfly's R points are one base
+// plus constants, which the LDS instructions take as immediate offsets.
+__device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
+constexpr int lds_size(int n) { return (n + (n >> 4) + 1 + 15) / 16 * 16; }
+// Slot of element base + q STRIDE: for STRIDE a multiple of 16, the base's
+// slot plus a constant (the compiler does not find this by itself).
+template <int STRIDE>
+__device__ __forceinline__ int lds_at(int base, int q) {
+  if constexpr (STRIDE % 16 == 0) return lds_ix(base) + q * (STRIDE + STRIDE / 16);
+  else return lds_ix(base + q * STRIDE);
+}
+// Slot of element base + q (q < R) for a base that is a multiple of R: for R
+// dividing 16 the run stays inside one group of 16.
+template <int R>
+__device__ __forceinline__ int lds_run(int base, int q) {
+  if constexpr (16 % R == 0) return lds_ix(base) + q;
+  else return lds_ix(base + q);
+}
 
 // A plan fixed at compile time: passes of radix Rs... (product N).  Pass s
 // runs after Ns(s) = rad[0] * .. * rad[s-1] points are combined and reads its
@@ -98,7 +114,7 @@ __device__ __forceinline__ void mid_pass(cplx<TC>* lds, int lane, const cplx<TC>
       const int jm = j % NS;
       v[i][0] = lds[lds_ix(j)];
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(j + q * nb)], tws[jm * R + q]);
+      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_at<nb>(j, q)], tws[jm * R + q]);
     }
   }
   tsync<T>();
@@ -109,7 +125,7 @@ __device__ __forceinline__ void mid_pass(cplx<TC>* lds, int lane, const cplx<TC>
       dft<R>(v[i]);
       const int jm = j % NS, dst = (j - jm) * R + jm;
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[lds_ix(dst + q * NS)] = v[i][q];
+      for (int q = 0; q < R; ++q) lds[lds_at<NS>(dst, q)] = v[i][q];
     }
   }
   tsync<T>();
@@ -151,7 +167,7 @@ __device__ __forceinline__ void rfft_first(cplx<TC>* lds, int Nt, int lane) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       v[i][q] = {(TC)0, (TC)0};
-      if (q < QL && (nb % T == 0 || j < nb) && j + q * nb < Nt) v[i][q] = lds[lds_ix(j + q * nb)];
+      if (q < QL && (nb % T == 0 || j < nb) && j + q * nb < Nt) v[i][q] = lds[lds_at<nb>(j, q)];
     }
   }
   tsync<T>();
@@ -161,21 +177,22 @@ __device__ __forceinline__ void rfft_first(cplx<TC>* lds, int Nt, int lane) {
     if (nb % T == 0 || j < nb) {
       dft<R>(v[i]);
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[lds_ix(j * R + q)] = v[i][q];
+      for (int q = 0; q < R; ++q) lds[lds_run<R>(j * R, q)] = v[i][q];
     }
   }
   tsync<T>();
 }
 
 // Bin k of both real series from Z_k and Z_{N-k}, rounded to the FFT format
-// and then to the next phase's: X = (Z_k + conj Z_{N-k}) / 2 goes to slab
-// slot k, Y = (Z_k - conj Z_{N-k}) / 2i to slot N/2 + 1 + k.
-template <bool HALF, int N, class TC>
-__device__ __forceinline__ void sep_bin(cplx<TC>* lds, int k, cplx<TC> zk, cplx<TC> zr, int r_fft, int r_next) {
+// and then to the next phase's: X = (Z_k + conj Z_{N-k}) / 2 goes to the
+// slot of element k, Y = (Z_k - conj Z_{N-k}) / 2i to that of N/2 + 1 + k.
+template <bool HALF, class TC>
+__device__ __forceinline__ void sep_bin(cplx<TC>* lds, int slot_x, int slot_y, cplx<TC> zk, cplx<TC> zr, int r_fft,
+                                        int r_next) {
   cplx<TC> X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
   cplx<TC> Y = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
-  lds[lds_ix(k)] = round_as<HALF>(round_as<HALF>(X, r_fft), r_next);
-  lds[lds_ix(N / 2 + 1 + k)] = round_as<HALF>(round_as<HALF>(Y, r_fft), r_next);
+  lds[slot_x] = round_as<HALF>(round_as<HALF>(X, r_fft), r_next);
+  lds[slot_y] = round_as<HALF>(round_as<HALF>(Y, r_fft), r_next);
 }
 
 // Last pass (Ns = nb, so jm = j) in paired units; the separated bins
@@ -195,11 +212,11 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
     const int j1 = u, j2 = partner_butterfly<nb>(u);
     v1[i][0] = lds[lds_ix(j1)];
 #pragma unroll
-    for (int q = 1; q < R; ++q) v1[i][q] = cmul(lds[lds_ix(j1 + q * nb)], tws[j1 * R + q]);
+    for (int q = 1; q < R; ++q) v1[i][q] = cmul(lds[lds_at<nb>(j1, q)], tws[j1 * R + q]);
     if (has_second<nb>(u)) {
       v2[i][0] = lds[lds_ix(j2)];
 #pragma unroll
-      for (int q = 1; q < R; ++q) v2[i][q] = cmul(lds[lds_ix(j2 + q * nb)], tws[j2 * R + q]);
+      for (int q = 1; q < R; ++q) v2[i][q] = cmul(lds[lds_at<nb>(j2, q)], tws[j2 * R + q]);
     }
   }
   tsync<T>();
@@ -213,17 +230,24 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
     if (u == 0) {
 #pragma unroll
       for (int q = 0; q < R; ++q)
-        if (q * nb <= hN) sep_bin<HALF, N>(lds, q * nb, v1[i][q], v1[i][(R - q) % R], r_fft, r_next);
+        if (q * nb <= hN)
+          sep_bin<HALF>(lds, lds_at<nb>(0, q), lds_at<nb>(hN + 1, q), v1[i][q], v1[i][(R - q) % R], r_fft, r_next);
       if constexpr (nb % 2 == 0) {
 #pragma unroll
         for (int q = 0; q < R; ++q)
-          if (j2 + q * nb <= hN) sep_bin<HALF, N>(lds, j2 + q * nb, v2[i][q], v2[i][R - 1 - q], r_fft, r_next);
+          if (j2 + q * nb <= hN)
+            sep_bin<HALF>(lds, lds_at<nb>(j2, q), lds_at<nb>(hN + 1 + j2, q), v2[i][q], v2[i][R - 1 - q], r_fft,
+                          r_next);
       }
     } else {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        if (j1 + q * nb <= hN) sep_bin<HALF, N>(lds, j1 + q * nb, v1[i][q], v2[i][R - 1 - q], r_fft, r_next);
-        if (j2 + q * nb <= hN) sep_bin<HALF, N>(lds, j2 + q * nb, v2[i][q], v1[i][R - 1 - q], r_fft, r_next);
+        if (j1 + q * nb <= hN)
+          sep_bin<HALF>(lds, lds_at<nb>(j1, q), lds_at<nb>(hN + 1 + j1, q), v1[i][q], v2[i][R - 1 - q], r_fft,
+                        r_next);
+        if (j2 + q * nb <= hN)
+          sep_bin<HALF>(lds, lds_at<nb>(j2, q), lds_at<nb>(hN + 1 + j2, q), v2[i][q], v1[i][R - 1 - q], r_fft,
+                        r_next);
       }
     }
   }
@@ -355,7 +379,7 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
       for (int q = 0; q < R; ++q) {
         const int k = q * nb;
         if (k <= hN) {
-          const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+          const cplx<TC> A = lds[lds_at<nb>(0, q)], B = lds[lds_at<nb>(hN + 1, q)];
           v1[i][q] = conj_z_direct(A, B);
           if (q != 0) v1[i][(R - q) % R] = conj_z_mirror(A, B);
         }
@@ -366,7 +390,7 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
         for (int q = 0; q < R; ++q) {
           const int k = j2 + q * nb;
           if (k <= hN) {
-            const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+            const cplx<TC> A = lds[lds_at<nb>(j2, q)], B = lds[lds_at<nb>(hN + 1 + j2, q)];
             v2[i][q] = conj_z_direct(A, B);
             if (R - 1 - q != q) v2[i][R - 1 - q] = conj_z_mirror(A, B);
           }
@@ -379,7 +403,7 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
       for (int q = 0; q < R; ++q) {
         const int k = j1 + q * nb;
         if (k <= hN) {
-          const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+          const cplx<TC> A = lds[lds_at<nb>(j1, q)], B = lds[lds_at<nb>(hN + 1 + j1, q)];
           v1[i][q] = conj_z_direct(A, B);
           v2[i][R - 1 - q] = conj_z_mirror(A, B);
         }
@@ -388,7 +412,7 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
       for (int q = 0; q < R; ++q) {
         const int k = j2 + q * nb;
         if (k <= hN) {
-          const cplx<TC> A = lds[lds_ix(k)], B = lds[lds_ix(hN + 1 + k)];
+          const cplx<TC> A = lds[lds_at<nb>(j2, q)], B = lds[lds_at<nb>(hN + 1 + j2, q)];
           v2[i][q] = conj_z_direct(A, B);
           v1[i][R - 1 - q] = conj_z_mirror(A, B);
         }
@@ -403,11 +427,11 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
     const int j1 = u, j2 = partner_butterfly<nb>(u);
     dft<R>(v1[i]);
 #pragma unroll
-    for (int q = 0; q < R; ++q) lds[lds_ix(j1 * R + q)] = v1[i][q];
+    for (int q = 0; q < R; ++q) lds[lds_run<R>(j1 * R, q)] = v1[i][q];
     if (has_second<nb>(u)) {
       dft<R>(v2[i]);
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[lds_ix(j2 * R + q)] = v2[i][q];
+      for (int q = 0; q < R; ++q) lds[lds_run<R>(j2 * R, q)] = v2[i][q];
     }
   }
   tsync<T>();
@@ -430,7 +454,7 @@ __device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, cons
     if ((nb % T != 0 && j >= nb) || j >= Nt) continue;
     v[i][0] = lds[lds_ix(j)];
 #pragma unroll
-    for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_ix(j + q * nb)], tws[j * R + q]);
+    for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_at<nb>(j, q)], tws[j * R + q]);
   }
   tsync<T>();
 #pragma unroll
@@ -443,7 +467,7 @@ __device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, cons
       const int t = j + q * nb;
       if (t < Nt) {  // W_t = N conj(y_t), y = a + i b
         const TC ra = round_as<HALF>(v[i][q].x * inv_n, r_ifft), rb = round_as<HALF>(-v[i][q].y * inv_n, r_ifft);
-        lds[lds_ix(t)] = {(TC)round_as<HALF>((double)ra, r_unpad), (TC)round_as<HALF>((double)rb, r_unpad)};
+        lds[lds_at<nb>(j, q)] = {(TC)round_as<HALF>((double)ra, r_unpad), (TC)round_as<HALF>((double)rb, r_unpad)};
       }
     }
   }
