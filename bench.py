@@ -381,11 +381,12 @@ def sbgemv_section(log):
     return rows
 
 
-def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000.0, budget_gib: float = 4.0):
+def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000.0, budget_gib: float = 16.0):
     """Poisson arrivals at `rate` req/s against 4 device-resident FP32
     operators; each request is forward or adjoint (50/50) with 1..32 vectors,
-    operator uniform.  Workspace budget `budget_gib` (at 4 GiB it binds: a
-    32-vector request on the largest operators needs 1.3-2.1 GB).  A second,
+    operator uniform.  Workspace budget `budget_gib` (16 GiB by default; at
+    4 GiB it binds: a 32-vector request on the largest operators needs 1.3-2.1
+    GB, and a coalesced 64-vector batch twice that).  A second,
     shorter run offers the same mix at 3/4 of the throughput the first one
     reached (`below_capacity`), where the latency is not dominated by
     queueing.  `capacity` is what the GPU can serve with one batch at a time:
@@ -558,8 +559,8 @@ def main() -> int:
                     help="skip the 64-right-hand-side GEMM measurement (Nt=512, Nd=128, Nm=4096)")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="measured duration of the serving run (after a 1 s warm-up); 0 skips it")
-    ap.add_argument("--serving-budget-gib", type=float, default=4.0,
-                    help="workspace budget of the serving run's server")
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0,
+                    help="workspace budget of the serving run's server (16 GiB of the 288 GB)")
     ap.add_argument("--json-out", default=None, help="also write the full record here")
     args = ap.parse_args()
     if args.no_oracle:

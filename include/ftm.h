@@ -261,9 +261,9 @@ ftm_status ftm_select_precision(ftm_operator op, int32_t adjoint, double toleran
  *                     float32 accumulation: 1 the FP32 MFMA, 2 the BF16 MFMA
  *                     on the three-term BF16 split of both operands (FP32
  *                     accuracy, fewer cycles; faster when the product is
- *                     compute bound), 0 the default (2 for the forward
- *                     product at 64-right-hand-side tiles, else 1); other
- *                     storage formats ignore it
+ *                     compute bound), 0 the default (2 at 64-right-hand-
+ *                     side tiles, for the adjoint only when Nd > 32; else
+ *                     1); other storage formats ignore it
  *   gemm_min_rhs[d]   smallest nrhs for which FTM_RHS_AUTO runs the GEMM (>= 2)
  *   ms[d]             the matvec time (milliseconds) of the last autotune at
  *                     these choices, 0 if none (read only) */

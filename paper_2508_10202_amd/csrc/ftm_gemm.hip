@@ -632,15 +632,21 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
     }
 }
 
-// FP32 storage on the BF16 matrix cores (three-term split): the tiling of the
-// half-precision adjoint kernel, with the spectrum and data tiles staged in
-// LDS as their three BF16 terms.
+// FP32 storage on the BF16 matrix cores (three-term split).  The spectrum
+// tile (32 sensors x 64 columns) is staged in LDS transposed, as separate
+// planes of the real and imaginary BF16 terms with the sensors contiguous, so
+// that a B operand (8 sensors of one column) is one 16-byte LDS read; each
+// thread loads 8 sensors of one column (lanes along the columns, coalesced).
+// The data tile (BM right-hand sides x 32 sensors) is staged the same way.
+// Re Y = xr fr + xi fi and Im Y = xi fr + xr (-fi).
 template <int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_x3_kernel(GemvArgs a, int nbb, int ncb) {
-  constexpr int BM = 16 * TB, NX = BM * RC / GEMM_THREADS;  // data-tile loads per thread
-  __shared__ uint32_t fs[3][RC][ADJ_BN + 4];                // (re | im << 16) per complex and term
-  __shared__ __align__(16) uint16_t xr16[3][BM][RC + 8];
-  __shared__ __align__(16) uint16_t xi16[3][BM][RC + 8];
+  constexpr int BM = 16 * TB, RP = RC + 8;  // LDS row pitch in 16-bit elements (16-byte aligned rows)
+  constexpr int NXT = BM * (RC / 8);        // data-tile tasks: 8 sensors of one right-hand side
+  __shared__ __align__(16) uint16_t fre[3][ADJ_BN][RP];
+  __shared__ __align__(16) uint16_t fim[3][ADJ_BN][RP];
+  __shared__ __align__(16) uint16_t xre[3][BM][RP];
+  __shared__ __align__(16) uint16_t xim[3][BM][RP];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * ncb;
   const int64_t k = wg / per_k;
@@ -656,88 +662,94 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_x3_kernel(GemvArgs a, i
 #pragma unroll
   for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
-  // on chunk r0: the spectrum tile (32 rows x 64 columns, two complex per
-  // 16-byte load) and the data tile (BM right-hand sides x 32 sensors).
-  float4 fv[4];
-  cplx<float> xv[NX];
+  // spectrum: thread (column tid mod 64, sensors 8 (tid / 64) ..+7); data:
+  // task e = tid + 256 q is (right-hand side e / 4, sensors 8 (e mod 4) ..+7).
+  // Sensor chunk r0 + RC is loaded while the matrix cores work on chunk r0.
+  const int fc = tid & 63, fr0 = (tid >> 6) * 8;
+  constexpr int NQ = (NXT + GEMM_THREADS - 1) / GEMM_THREADS;
+  cplx<float> fv[8], xv[NQ][8];
   auto load_chunk = [&](int r0) {
+    const int c = c0 + fc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + GEMM_THREADS * q;
-      const int row = idx >> 5, col = (idx & 31) * 2;
-      const int r = r0 + row, c = c0 + col;
-      fv[q] = (r < a.Nd && c < a.ld) ? __builtin_bit_cast(float4, load_stream(Fk + (int64_t)r * a.ld + c))
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < 8; ++i) {
+      const int r = r0 + fr0 + i;
+      fv[i] = (r < a.Nd && c < a.ld) ? Fk[(int64_t)r * a.ld + c] : cplx<float>{0.f, 0.f};
     }
 #pragma unroll
-    for (int q = 0; q < NX; ++q) {
-      const int idx = tid + GEMM_THREADS * q;
-      const int bl = idx >> 5, rr = idx & 31;
-      const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
-      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + GEMM_THREADS * q;
+      const int b = min(b0 + e / 4, a.nrhs - 1), rs = r0 + 8 * (e & 3);
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        xv[q][i] = (NXT % GEMM_THREADS == 0 || e < NXT) && rs + i < a.Nd ? X[(int64_t)b * a.x_rhs_stride + rs + i]
+                                                                         : cplx<float>{0.f, 0.f};
     }
+  };
+  // the three terms of 8 values as three 16-byte rows of LDS
+  auto put8 = [](uint16_t* d0, uint16_t* d1, uint16_t* d2, const float (&v)[8]) {
+    uint32_t wv[3][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const Split3 lo = split3(v[2 * i]), hi = split3(v[2 * i + 1]);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) wv[p][i] = pack2(lo.h[p], hi.h[p]);
+    }
+    *reinterpret_cast<uint4*>(d0) = make_uint4(wv[0][0], wv[0][1], wv[0][2], wv[0][3]);
+    *reinterpret_cast<uint4*>(d1) = make_uint4(wv[1][0], wv[1][1], wv[1][2], wv[1][3]);
+    *reinterpret_cast<uint4*>(d2) = make_uint4(wv[2][0], wv[2][1], wv[2][2], wv[2][3]);
   };
   load_chunk(0);
   for (int r0 = 0; r0 < a.Nd; r0 += RC) {
+    {
+      float vr[8], vi[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + GEMM_THREADS * q;
-      const int row = idx >> 5, col = (idx & 31) * 2;
-      const Split3 s0r = split3(fv[q].x), s0i = split3(fv[q].y), s1r = split3(fv[q].z), s1i = split3(fv[q].w);
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        fs[p][row][col] = pack2(s0r.h[p], s0i.h[p]);
-        fs[p][row][col + 1] = pack2(s1r.h[p], s1i.h[p]);
+      for (int i = 0; i < 8; ++i) {
+        vr[i] = fv[i].x;
+        vi[i] = fv[i].y;
       }
+      put8(&fre[0][fc][fr0], &fre[1][fc][fr0], &fre[2][fc][fr0], vr);
+      put8(&fim[0][fc][fr0], &fim[1][fc][fr0], &fim[2][fc][fr0], vi);
     }
 #pragma unroll
-    for (int q = 0; q < NX; ++q) {
-      const int idx = tid + GEMM_THREADS * q;
-      const int bl = idx >> 5, rr = idx & 31;
-      const Split3 sr = split3(xv[q].x), si = split3(xv[q].y);
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + GEMM_THREADS * q;
+      if (NXT % GEMM_THREADS != 0 && e >= NXT) continue;
+      const int bl = e / 4, rs = 8 * (e & 3);
+      float vr[8], vi[8];
 #pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        xr16[p][bl][rr] = (uint16_t)sr.h[p];
-        xi16[p][bl][rr] = (uint16_t)si.h[p];
+      for (int i = 0; i < 8; ++i) {
+        vr[i] = xv[q][i].x;
+        vi[i] = xv[q][i].y;
       }
+      put8(&xre[0][bl][rs], &xre[1][bl][rs], &xre[2][bl][rs], vr);
+      put8(&xim[0][bl][rs], &xim[1][bl][rs], &xim[2][bl][rs], vi);
     }
     __syncthreads();
     if (r0 + RC < a.Nd) load_chunk(r0 + RC);
-    // B operands: the terms of fr and fi of sensors 8 g .. 8 g + 7 at this
-    // lane's column
-    bf16x8 fr[3], fi[3];
+    // B operands: the terms of fr, fi and -fi of sensors 8 g .. 8 g + 7 at
+    // this lane's column
+    bf16x8 fr[3], fi[3], fn[3];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-      uint4 ufr, ufi;
-      uint32_t* pr = reinterpret_cast<uint32_t*>(&ufr);
-      uint32_t* pi = reinterpret_cast<uint32_t*>(&ufi);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t w0 = fs[p][8 * g + 2 * q][w * 16 + l16], w1 = fs[p][8 * g + 2 * q + 1][w * 16 + l16];
-        pr[q] = (w0 & 0xffffu) | (w1 << 16);
-        pi[q] = (w0 >> 16) | (w1 & 0xffff0000u);
-      }
-      fr[p] = __builtin_bit_cast(bf16x8, ufr);
-      fi[p] = __builtin_bit_cast(bf16x8, ufi);
+      const uint4 ur = *reinterpret_cast<const uint4*>(&fre[p][w * 16 + l16][8 * g]);
+      const uint4 ui = *reinterpret_cast<const uint4*>(&fim[p][w * 16 + l16][8 * g]);
+      fr[p] = __builtin_bit_cast(bf16x8, ur);
+      fi[p] = __builtin_bit_cast(bf16x8, ui);
+      fn[p] = __builtin_bit_cast(bf16x8, make_uint4(ui.x ^ 0x80008000u, ui.y ^ 0x80008000u, ui.z ^ 0x80008000u,
+                                                    ui.w ^ 0x80008000u));
     }
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
-      bf16x8 vxr[3], vxi[3], vxn[3];
+      bf16x8 vxr[3], vxi[3];
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const uint4 uxr = *reinterpret_cast<const uint4*>(&xr16[p][16 * t + l16][8 * g]);
-        const uint4 uxi = *reinterpret_cast<const uint4*>(&xi16[p][16 * t + l16][8 * g]);
-        const uint4 uxn = make_uint4(uxr.x ^ 0x80008000u, uxr.y ^ 0x80008000u, uxr.z ^ 0x80008000u,
-                                     uxr.w ^ 0x80008000u);
-        vxr[p] = __builtin_bit_cast(bf16x8, uxr);
-        vxi[p] = __builtin_bit_cast(bf16x8, uxi);
-        vxn[p] = __builtin_bit_cast(bf16x8, uxn);
+        vxr[p] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&xre[p][16 * t + l16][8 * g]));
+        vxi[p] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&xim[p][16 * t + l16][8 * g]));
       }
       re[t] = mma_split(vxr, fr, re[t]);
       re[t] = mma_split(vxi, fi, re[t]);
       im[t] = mma_split(vxi, fr, im[t]);
-      im[t] = mma_split(vxn, fi, im[t]);
+      im[t] = mma_split(vxr, fn, im[t]);
     }
     __syncthreads();
   }
@@ -981,8 +993,9 @@ static hipError_t gemm_adj_go(int fdt, const GemvArgs& a, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
-    case DT_F32:  // the split-term kernel only when asked for (kind 2)
-      if (a.gemm_kind == 2) hipLaunchKernelGGL((gemm_adj_x3_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
+    case DT_F32:  // the split-term kernel by default at 64-RHS tiles with more than one sensor chunk
+      if (a.gemm_kind == 2 || (a.gemm_kind == 0 && TB == 4 && a.Nd > RC))
+        hipLaunchKernelGGL((gemm_adj_x3_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
       else hipLaunchKernelGGL((gemm_adj_f32_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
       break;
     case DT_F16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, ncb); break;
