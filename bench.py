@@ -230,9 +230,16 @@ def multi_rhs_section(log):
         p = timed(lambda: (op.matvec(Mt, out=Yd), op.rmatvec(Dt, out=Ym)))
         e_f = oracle.relative_l2(Yd[pick].cpu().numpy(), ref_d)
         e_a = oracle.relative_l2(Ym[pick].cpu().numpy(), ref_m)
-        gemm_bytes = s.K * s.Nd * s.Nm * fbytes + s.K * B * (s.Nm + s.Nd) * 8
+        # bytes per complex entry of the product's input and output as the
+        # library stores them (float64 between float64 phases, 16 bits for the
+        # input of a half-precision product, float32 otherwise)
+        body = prec.split("+")[0]
+        xb = 16 if body[1] == body[2] == "d" else (4 if body[2] in "hb" else 8)
+        yb = 16 if body[2] == body[3] == "d" else 8
         rec = {"peak_tflops": peak}
         for name, kms, err, base in (("fwd", p["fwd"], e_f, base_f), ("adj", p["adj"], e_a, base_a)):
+            n_in, n_out = (s.Nd, s.Nm) if name == "adj" else (s.Nm, s.Nd)
+            gemm_bytes = s.K * s.Nd * s.Nm * fbytes + s.K * B * (n_in * xb + n_out * yb)
             t = kms[1] * 1e-3
             rec[name] = {"kernels_ms": [round(x, 4) for x in kms], "matvec_ms": round(sum(kms), 4),
                          "gemm_tflops": round(flops / t / 1e12, 2), "mfma_frac": round(flops / t / 1e12 / peak, 4),

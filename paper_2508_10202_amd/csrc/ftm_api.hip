@@ -280,9 +280,17 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   // Intermediates between phases are stored in float64 only when both
   // neighbouring phases are float64; otherwise the producing kernel applies
   // both phases' roundings and stores float32, which holds every such value
-  // exactly (FP16 and BF16 values are float32 values).
+  // exactly (FP16 and BF16 values are float32 values).  On the matrix-core
+  // path of a half-precision product its input is stored in 16 bits in the
+  // product's format, in which the producer's last rounding left it: the
+  // product reads half the bytes.  Its output stays float32 (measured: the
+  // inverse transform reading 16-bit rows, 64 bytes per tile row, loses more
+  // than the product saves).
   const bool x_hat64 = p.fft == DT_F64 && p.gemv == DT_F64;
   const bool y_hat64 = p.gemv == DT_F64 && p.ifft == DT_F64;
+  const bool st16 = ex.use_gemm && (p.gemv == DT_F16 || p.gemv == DT_BF16) && p.accum != DT_F64;
+  const int x_st = st16 ? ST_16 : (x_hat64 ? ST_F64 : ST_F32);
+  const int y_st = y_hat64 ? ST_F64 : ST_F32;
   const int64_t Sx = adjoint ? op->Nd : op->Nm, Sy = adjoint ? op->Nm : op->Nd;
   const int ldx = adjoint ? op->ldd : op->ldm, ldy = adjoint ? op->ldm : op->ldd;
   void* xhat = adjoint ? ws.dhat : ws.mhat;
@@ -309,7 +317,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ra.r_next = p.gemv;
   Profiler prof(op, st, adjoint ? 1 : 0, ex.profile);
   prof.mark(0);
-  FTM_HIP(launch_rfft(p.fft == DT_F64, x_hat64, ra, op->fft_in(p.fft == DT_F64), ex.fft_shape_in, st));
+  FTM_HIP(launch_rfft(p.fft == DT_F64, x_st, ra, op->fft_in(p.fft == DT_F64), ex.fft_shape_in, st));
 
   GemvArgs ga{};
   ga.F = F;
@@ -330,6 +338,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ga.variant = ex.gemv_variant;
   ga.rhs_tile = ex.gemm_tile;
   ga.gemm_kind = ex.gemm_kind;
+  ga.x16 = st16 ? 1 : 0;
   const bool acc64 = p.accum == DT_F64;
   prof.mark(1);
   if (ex.use_gemm) {
@@ -356,7 +365,7 @@ ftm_status ftm_rt::run_matvec(ftm_operator op, bool adjoint, const Exec& ex, con
   ia.r_ifft = p.ifft;
   ia.r_unpad = p.unpad;
   prof.mark(2);
-  FTM_HIP(launch_irfft(y_hat64, p.ifft == DT_F64, ia, op->fft_out(p.ifft == DT_F64), ex.fft_shape_out, st));
+  FTM_HIP(launch_irfft(y_st, p.ifft == DT_F64, ia, op->fft_out(p.ifft == DT_F64), ex.fft_shape_out, st));
   prof.mark(3);
   return FTM_OK;
 }
@@ -505,7 +514,7 @@ ftm_status ftm_setup_operator_strided(ftm_operator* out, const double* F, int64_
     ra.ld_row = op->ldm;
     ra.r_pad = ra.r_fft = ra.r_next = DT_F64;
     ra.pad_to = 0;  // the spectrum's padding is cleared above
-    e = launch_rfft(true, true, ra, op->fft_in(true), 0, st);
+    e = launch_rfft(true, ST_F64, ra, op->fft_in(true), 0, st);
     if (e != hipSuccess) return bail(fail_hip("setup transform", e));
 
     const uint32_t keep = needed_mask(pf, pa) | spectra;

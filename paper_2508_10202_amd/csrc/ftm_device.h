@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #ifndef FTM_STREAM_NT
 #define FTM_STREAM_NT 1
 #endif
@@ -101,6 +103,24 @@ __device__ __forceinline__ float round_as(float x, int dt) {
 template <bool HALF, class T>
 __device__ __forceinline__ cplx<T> round_as(cplx<T> a, int dt) {
   return {round_as<HALF>(a.x, dt), round_as<HALF>(a.y, dt)};
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit storage of a transformed vector between two phases, in FP16 or BF16
+// (the format is a launch argument).  Only values exact in that format are
+// stored, so the conversion is exact.
+struct h16 {
+  uint16_t b;
+};
+__device__ __forceinline__ h16 to_h16(float v, int dt) {
+  return {dt == DT_BF16 ? (uint16_t)(__float_as_uint(v) >> 16) : __half_as_ushort(__float2half_rn(v))};
+}
+__device__ __forceinline__ h16 to_h16(double v, int dt) { return to_h16((float)v, dt); }
+// a complex value of type T stored as cplx<TS> (TS = h16: in format dt)
+template <class TS, class T>
+__device__ __forceinline__ cplx<TS> to_store(cplx<T> v, int dt) {
+  if constexpr (std::is_same<TS, h16>::value) return {to_h16(v.x, dt), to_h16(v.y, dt)};
+  else return {(TS)v.x, (TS)v.y};
 }
 
 // ---------------------------------------------------------------------------

@@ -212,7 +212,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
       if (!odd) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
       else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
       X = round_as<HALF>(round_as<HALF>(X, a.r_fft), a.r_next);
-      *o = {(TO)X.x, (TO)X.y};  // one 16/8-byte store
+      *o = to_store<TO>(X, a.r_next);  // one 16/8/4-byte store (16-bit: exact in format r_next)
     }
   }
   // the last pair block of a right-hand side also clears the padding columns
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     cplx<TO>* outb = reinterpret_cast<cplx<TO>*>(a.out);
     for (int i = tid; i < K * npad; i += TH) {
       const int k = i / npad;
-      outb[k * a.out_k_stride + b * a.out_rhs_stride + a.S + (i - k * npad)] = {(TO)0, (TO)0};
+      outb[k * a.out_k_stride + b * a.out_rhs_stride + a.S + (i - k * npad)] = cplx<TO>{};
     }
   }
 }
@@ -388,9 +388,9 @@ static hipError_t rfft_go(const RfftArgs& a, const FftPlan& plan, const void* tw
 // length; the build compiles exactly this list).
 #define FTM_FIXED_LENGTHS(X) X(128) X(256) X(400) X(512) X(1024) X(2000)
 #define FTM_DECLARE_FIXED(n)                                                                                  \
-  bool launch_rfft_fixed_##n(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan, const void* tw, \
+  bool launch_rfft_fixed_##n(bool tc64, int out_st, const RfftArgs& a, const FftPlan& plan, const void* tw,  \
                              int shape, hipStream_t st, hipError_t* err);                                   \
-  bool launch_irfft_fixed_##n(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan, const void* tw, \
+  bool launch_irfft_fixed_##n(int in_st, bool tc64, const IrfftArgs& a, const FftPlan& plan, const void* tw, \
                               int shape, hipStream_t st, hipError_t* err);
 FTM_FIXED_LENGTHS(FTM_DECLARE_FIXED)
 #undef FTM_DECLARE_FIXED
@@ -402,18 +402,23 @@ bool fft_has_fixed(int N) {
   return false;
 }
 
-hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlans& pl, int shape, hipStream_t st) {
+hipError_t launch_rfft(bool tc64, int out_st, const RfftArgs& a, const FftPlans& pl, int shape, hipStream_t st) {
   if (shape != FFT_SHAPE_GENERIC) {
     hipError_t e = hipSuccess;
     const FftPlan& fp = *pl.fixed;
 #define FTM_TRY_FIXED(n) \
-  if (fp.N == n && launch_rfft_fixed_##n(tc64, out64, a, fp, pl.fixed_tw, shape, st, &e)) return e;
+  if (fp.N == n && launch_rfft_fixed_##n(tc64, out_st, a, fp, pl.fixed_tw, shape, st, &e)) return e;
     FTM_FIXED_LENGTHS(FTM_TRY_FIXED)
 #undef FTM_TRY_FIXED
   }
   const FftPlan& gp = *pl.generic;
   const void* tw = pl.generic_tw;
-  if (tc64) return out64 ? rfft_go<double, double>(a, gp, tw, st) : rfft_go<double, float>(a, gp, tw, st);
+  if (tc64) {
+    if (out_st == ST_F64) return rfft_go<double, double>(a, gp, tw, st);
+    if (out_st == ST_16) return rfft_go<double, h16>(a, gp, tw, st);
+    return rfft_go<double, float>(a, gp, tw, st);
+  }
+  if (out_st == ST_16) return rfft_go<float, h16>(a, gp, tw, st);
   return rfft_go<float, float>(a, gp, tw, st);
 }
 
@@ -453,18 +458,19 @@ static hipError_t irfft_go(const IrfftArgs& a, const FftPlan& plan, const void* 
   }
 }
 
-hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlans& pl, int shape, hipStream_t st) {
+hipError_t launch_irfft(int in_st, bool tc64, const IrfftArgs& a, const FftPlans& pl, int shape, hipStream_t st) {
   if (shape != FFT_SHAPE_GENERIC) {
     hipError_t e = hipSuccess;
     const FftPlan& fp = *pl.fixed;
 #define FTM_TRY_FIXED(n) \
-  if (fp.N == n && launch_irfft_fixed_##n(in64, tc64, a, fp, pl.fixed_tw, shape, st, &e)) return e;
+  if (fp.N == n && launch_irfft_fixed_##n(in_st, tc64, a, fp, pl.fixed_tw, shape, st, &e)) return e;
     FTM_FIXED_LENGTHS(FTM_TRY_FIXED)
 #undef FTM_TRY_FIXED
   }
   const FftPlan& gp = *pl.generic;
   const void* tw = pl.generic_tw;
-  if (tc64) return in64 ? irfft_go<double, double>(a, gp, tw, st) : irfft_go<float, double>(a, gp, tw, st);
+  if (in_st == ST_16) return hipErrorInvalidValue;  // not a storage the inverse transform reads
+  if (tc64) return in_st == ST_F64 ? irfft_go<double, double>(a, gp, tw, st) : irfft_go<float, double>(a, gp, tw, st);
   return irfft_go<float, float>(a, gp, tw, st);
 }
 

@@ -335,12 +335,9 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
     }
     const bool pad = s >= a.S;
     for (int k = tid / C; k <= N / 2; k += ROWS) {
-      cplx<TO> w = {(TO)0, (TO)0};
-      if (!pad) {
-        const cplx<TC> z = slab[lds_ix(off + k)];
-        w = {(TO)z.x, (TO)z.y};
-      }
-      o[(int64_t)k * a.out_k_stride] = w;
+      cplx<TC> z = {(TC)0, (TC)0};
+      if (!pad) z = slab[lds_ix(off + k)];
+      o[(int64_t)k * a.out_k_stride] = to_store<TO>(z, a.r_next);  // 16-bit: exact in format r_next
     }
   }
 }
@@ -497,7 +494,7 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = k0 + u * ROWS;
-        v[u] = (live && k <= hN) ? in[(int64_t)k * a.in_k_stride] : cplx<TI>{(TI)0, (TI)0};
+        v[u] = (live && k <= hN) ? in[(int64_t)k * a.in_k_stride] : cplx<TI>{};
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -596,7 +593,6 @@ constexpr int tile_columns(int shape) {
   while (c / 2 * threads_per_transform<TC>() > 1024) c /= 2;
   return shape == 2 ? c / 2 : c;
 }
-
 template <class P>
 bool same_plan(const FftPlan& plan) {
   if (plan.N != P::N || plan.nst != P::nst) return false;
@@ -659,23 +655,36 @@ hipError_t irfft_go(const IrfftArgs& a, const void* tw, hipStream_t st) {
 // the operator's plan differs.  shape: 1 the larger tile, 2 the smaller, 0
 // the larger unless it gives fewer than 4 tiles per CU (the smaller tile then
 // spreads the transform over more workgroups; measured faster at such sizes).
-bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, bool out64, const RfftArgs& a, const FftPlan& plan,
+bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, int out_st, const RfftArgs& a, const FftPlan& plan,
                                                 const void* tw, int shape, hipStream_t st, hipError_t* err) {
   if (!(tc64 ? same_plan<PlanF64>(plan) : same_plan<PlanF32>(plan))) return false;
   const bool alt = shape == 2 || (shape == 0 && few_tiles(a.S, a.nrhs, tc64));
-  if (tc64 && out64) *err = alt ? rfft_go<double, double, 2>(a, tw, st) : rfft_go<double, double, 1>(a, tw, st);
-  else if (tc64) *err = alt ? rfft_go<double, float, 2>(a, tw, st) : rfft_go<double, float, 1>(a, tw, st);
-  else *err = alt ? rfft_go<float, float, 2>(a, tw, st) : rfft_go<float, float, 1>(a, tw, st);
+#define FTM_RGO(TC, TO) *err = alt ? rfft_go<TC, TO, 2>(a, tw, st) : rfft_go<TC, TO, 1>(a, tw, st)
+  if (tc64) {
+    if (out_st == ST_F64) FTM_RGO(double, double);
+    else if (out_st == ST_16) FTM_RGO(double, h16);
+    else FTM_RGO(double, float);
+  } else {
+    if (out_st == ST_16) FTM_RGO(float, h16);
+    else FTM_RGO(float, float);
+  }
+#undef FTM_RGO
   return true;
 }
 
-bool FTM_CAT(launch_irfft_fixed_, FTM_FIXED_N)(bool in64, bool tc64, const IrfftArgs& a, const FftPlan& plan,
+bool FTM_CAT(launch_irfft_fixed_, FTM_FIXED_N)(int in_st, bool tc64, const IrfftArgs& a, const FftPlan& plan,
                                                  const void* tw, int shape, hipStream_t st, hipError_t* err) {
   if (!(tc64 ? same_plan<PlanI64>(plan) : same_plan<PlanI32>(plan))) return false;
   const bool alt = shape == 2 || (shape == 0 && few_tiles(a.S, a.nrhs, tc64));
-  if (tc64 && in64) *err = alt ? irfft_go<double, double, 2>(a, tw, st) : irfft_go<double, double, 1>(a, tw, st);
-  else if (tc64) *err = alt ? irfft_go<float, double, 2>(a, tw, st) : irfft_go<float, double, 1>(a, tw, st);
-  else *err = alt ? irfft_go<float, float, 2>(a, tw, st) : irfft_go<float, float, 1>(a, tw, st);
+#define FTM_IGO(TI, TC) *err = alt ? irfft_go<TI, TC, 2>(a, tw, st) : irfft_go<TI, TC, 1>(a, tw, st)
+  if (in_st == ST_16) return false;  // not a storage the inverse transform reads
+  if (tc64) {
+    if (in_st == ST_F64) FTM_IGO(double, double);
+    else FTM_IGO(float, double);
+  } else {
+    FTM_IGO(float, float);
+  }
+#undef FTM_IGO
   return true;
 }
 

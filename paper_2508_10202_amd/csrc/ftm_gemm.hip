@@ -218,12 +218,12 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
 // ---------------------------------------------------------------------------
 // forward, FP16/BF16 storage: MFMA 16x16x32 (K' = 32 reals per instruction)
 // ---------------------------------------------------------------------------
-template <class S, int TB>
+template <class S, int TB, class TX>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, int nbb, int nrb) {
   using M = MfmaOf<S>;
   using H = typename M::half_t;
   constexpr int BM = 16 * TB;
-  __shared__ uint16_t xs[BM][KC + 8];  // X' in 16-bit, 64 reals per chunk
+  __shared__ __align__(16) uint16_t xs[BM][KC + 8];  // X' in 16-bit, 64 reals per chunk
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * nrb;
   const int64_t k = wg / per_k;
@@ -233,7 +233,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
   const int kr = 2 * a.ld;
 
-  const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
+  // X' is float32, or 16-bit values of the product's format (TX = h16)
+  const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + 2 * k * a.x_k_stride;
   const int64_t xrow = 2 * a.x_rhs_stride;
   const uint16_t* __restrict__ Fk = reinterpret_cast<const uint16_t*>(a.F) + 2 * k * a.f_k_stride;
   const int r_me = min(r0 + l16, a.Nd - 1);
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   // 4 (e mod 16) .. +3, so 16 threads read one row's 256 B.  Chunk kc + KC is
   // loaded into registers while the matrix cores work on chunk kc.
   int st_row[TB], st_col[TB];
-  const float* __restrict__ xsrc[TB];
+  const TX* __restrict__ xsrc[TB];
 #pragma unroll
   for (int q = 0; q < TB; ++q) {
     const int e = threadIdx.x + GEMM_THREADS * q;
@@ -255,13 +256,14 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
     st_col[q] = (e & 15) * 4;
     xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
   }
-  float4 xv[TB];
+  using XV = typename std::conditional<std::is_same<TX, h16>::value, uint2, float4>::type;  // 4 reals
+  XV xv[TB];
   uint4 fn[2];
   auto load_chunk = [&](int kc) {
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
       const int col = kc + st_col[q];
-      xv[q] = col < kr ? *reinterpret_cast<const float4*>(xsrc[q] + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+      xv[q] = col < kr ? *reinterpret_cast<const XV*>(xsrc[q] + col) : XV{};
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -274,10 +276,14 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
       uint16_t* d = &xs[st_row[q]][st_col[q]];
-      d[0] = (uint16_t)to_bits16<H>(xv[q].x);
-      d[1] = (uint16_t)to_bits16<H>(xv[q].y);
-      d[2] = (uint16_t)to_bits16<H>(xv[q].z);
-      d[3] = (uint16_t)to_bits16<H>(xv[q].w);
+      if constexpr (std::is_same<TX, h16>::value) {
+        *reinterpret_cast<uint2*>(d) = xv[q];  // already the product's 16-bit values
+      } else {
+        d[0] = (uint16_t)to_bits16<H>(xv[q].x);
+        d[1] = (uint16_t)to_bits16<H>(xv[q].y);
+        d[2] = (uint16_t)to_bits16<H>(xv[q].z);
+        d[3] = (uint16_t)to_bits16<H>(xv[q].w);
+      }
     }
     uint4 fv[2] = {fn[0], fn[1]};
     __syncthreads();
@@ -314,10 +320,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) {
-        float* y = Y + 2 * (b * a.y_rhs_stride + r);
-        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
-      }
+      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + r), re[t][v], im[t][v], a.r_gemv, a.r_next);
     }
 }
 
@@ -527,7 +530,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
 }
 
 // FP16/BF16 storage: MFMA 16x16x32, one k-step of 32 sensors per chunk.
-template <class S, int TB>
+template <class S, int TB, class TX>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, int nbb, int ncb) {
   using M = MfmaOf<S>;
   using H = typename M::half_t;
@@ -543,7 +546,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, c0 = cb * ADJ_BN;
 
-  const cplx<float>* __restrict__ X = reinterpret_cast<const cplx<float>*>(a.x) + k * a.x_k_stride;
+  const cplx<TX>* __restrict__ X = reinterpret_cast<const cplx<TX>*>(a.x) + k * a.x_k_stride;
   const uint32_t* __restrict__ Fk = reinterpret_cast<const uint32_t*>(a.F) + k * a.f_k_stride;
 
   f32x4 re[TB], im[TB];
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   // on chunk r0: the spectrum tile (32 rows x 64 columns, four complex per
   // 16-byte load) and the data tile (BM right-hand sides x 32 sensors).
   uint4 fv[2];
-  cplx<float> xv[NX];
+  cplx<TX> xv[NX];
   auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
-      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<float>{0.f, 0.f};
+      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<TX>{};
     }
   };
   load_chunk(0);
@@ -586,8 +589,13 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
     for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int bl = idx >> 5, rr = idx & 31;
-      xr16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].x);  // exact: x holds values of the 16-bit format
-      xi16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].y);
+      if constexpr (std::is_same<TX, h16>::value) {
+        xr16[bl][rr] = xv[q].x.b;  // already the product's 16-bit values
+        xi16[bl][rr] = xv[q].y.b;
+      } else {
+        xr16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].x);  // exact: x holds values of the 16-bit format
+        xi16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].y);
+      }
     }
     __syncthreads();
     if (r0 + RC < a.Nd) load_chunk(r0 + RC);
@@ -979,8 +987,14 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
     case DT_F32: hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB>), grid, block, 0, st, a, nbb, nrb); break;
-    case DT_F16: hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, nrb); break;
-    case DT_BF16: hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, nrb); break;
+    case DT_F16:
+      if (a.x16) hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB, h16>), grid, block, 0, st, a, nbb, nrb);
+      else hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB, float>), grid, block, 0, st, a, nbb, nrb);
+      break;
+    case DT_BF16:
+      if (a.x16) hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB, h16>), grid, block, 0, st, a, nbb, nrb);
+      else hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB, float>), grid, block, 0, st, a, nbb, nrb);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -998,8 +1012,14 @@ static hipError_t gemm_adj_go(int fdt, const GemvArgs& a, hipStream_t st) {
         hipLaunchKernelGGL((gemm_adj_x3_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
       else hipLaunchKernelGGL((gemm_adj_f32_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
       break;
-    case DT_F16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, ncb); break;
-    case DT_BF16: hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, ncb); break;
+    case DT_F16:
+      if (a.x16) hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB, h16>), grid, block, 0, st, a, nbb, ncb);
+      else hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB, float>), grid, block, 0, st, a, nbb, ncb);
+      break;
+    case DT_BF16:
+      if (a.x16) hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB, h16>), grid, block, 0, st, a, nbb, ncb);
+      else hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB, float>), grid, block, 0, st, a, nbb, ncb);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -19,6 +19,11 @@ constexpr int FFT_POINTS = FTM_FFT_POINTS;
 // fewer than 4 tiles per CU), 1 and 2 the fixed-plan kernels' larger and
 // smaller column tiles, 3 the runtime-plan kernels.
 constexpr int FFT_SHAPES = 4;
+// Storage of a transformed vector between phases: float32, float64, or 16
+// bits in the product's FP16/BF16 format (the input of a half-precision
+// product on the matrix cores, where every stored value is exact in that
+// format).
+enum : int { ST_F32 = 0, ST_F64 = 1, ST_16 = 2 };
 constexpr int FFT_SHAPE_GENERIC = 3;
 // Whether length N has fixed-plan kernels.
 bool fft_has_fixed(int N);
@@ -108,6 +113,7 @@ struct GemvArgs {
   int variant;   // kernel variant (tile shape), 0 = default; see ftm_gemv.hip
   int rhs_tile;  // right-hand sides per GEMM tile: 16, 32 or 64 (0: by nrhs)
   int gemm_kind; // FP32-storage GEMM: 1 FP32 MFMA, 2 BF16 MFMA on split terms, 0 default
+  int x16;       // half-precision GEMM: x stored in 16 bits (ST_16) in the product's format
 };
 
 // Number of tile-shape variants of the matrix-vector kernels.
@@ -124,8 +130,8 @@ struct FftPlans {
   const void* generic_tw;
 };
 // shape: the kernel choice (0 = default; FFT_SHAPES above).
-hipError_t launch_rfft(bool tc64, bool out64, const RfftArgs& a, const FftPlans& pl, int shape, hipStream_t st);
-hipError_t launch_irfft(bool in64, bool tc64, const IrfftArgs& a, const FftPlans& pl, int shape, hipStream_t st);
+hipError_t launch_rfft(bool tc64, int out_st, const RfftArgs& a, const FftPlans& pl, int shape, hipStream_t st);
+hipError_t launch_irfft(int in_st, bool tc64, const IrfftArgs& a, const FftPlans& pl, int shape, hipStream_t st);
 hipError_t launch_gemv_fwd(int fdt, bool acc64, bool in64, bool out64, const GemvArgs& a,
                            hipStream_t st);
 hipError_t launch_gemv_adj(int fdt, bool acc64, bool in64, bool out64, const GemvArgs& a,
