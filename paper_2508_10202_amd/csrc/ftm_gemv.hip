@@ -10,7 +10,9 @@
 //
 // Forward (short and wide Fhat_k, Nd << Nm): a workgroup owns R consecutive
 // rows of one frequency and sweeps all columns; every lane keeps R running
-// sums and reuses each input value for R rows.  Per-lane sums are reduced
+// sums and reuses each input value for R rows (a half-precision product reads
+// its input in the same 16-bit format, 4 values per 16-byte load, which
+// halves the input's share of the reads).  Per-lane sums are reduced
 // with cross-lane shuffles and then across the 4 waves through LDS, in a fixed
 // order (deterministic, no atomics).
 //
@@ -122,7 +124,10 @@ __global__ __launch_bounds__(GEMV_THREADS) void gemv_fwd_kernel(GemvArgs a, int 
       fr[r] = load_stream(Fk + (int64_t)rr * a.ld + (int64_t)cv * V);
     }
     cplx<TA> xv[V];
-    load_in<TI, TA, V>(xk + (int64_t)cv * V, xv);
+    if constexpr (std::is_same<TI, h16>::value)  // V = 4 values in the spectrum's 16-bit format
+      Chunk<S, TA>::decode(*reinterpret_cast<const uint4*>(xk + (int64_t)cv * V), xv);
+    else
+      load_in<TI, TA, V>(xk + (int64_t)cv * V, xv);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       cplx<TA> f[V];
@@ -300,9 +305,17 @@ static hipError_t gemv_dispatch(int fdt, bool acc64, bool in64, bool out64, cons
       FTM_GO(s_f32, float, float, float);
     case DT_F16:
       if (in64 || out64 || acc64) break;
+      if constexpr (!ADJ) {
+        if (a.x16) return fwd_go<s_f16, float, h16, float>(a, st);
+      }
+      if (a.x16) break;
       FTM_GO(s_f16, float, float, float);
     case DT_BF16:
       if (in64 || out64 || acc64) break;
+      if constexpr (!ADJ) {
+        if (a.x16) return fwd_go<s_bf16, float, h16, float>(a, st);
+      }
+      if (a.x16) break;
       FTM_GO(s_bf16, float, float, float);
     default: break;
   }

@@ -113,7 +113,7 @@ struct GemvArgs {
   int variant;   // kernel variant (tile shape), 0 = default; see ftm_gemv.hip
   int rhs_tile;  // right-hand sides per GEMM tile: 16, 32 or 64 (0: by nrhs)
   int gemm_kind; // FP32-storage GEMM: 1 FP32 MFMA, 2 BF16 MFMA on split terms, 0 default
-  int x16;       // half-precision GEMM: x stored in 16 bits (ST_16) in the product's format
+  int x16;       // half-precision GEMM or forward GEMV: x stored in 16 bits (ST_16) in the product's format
 };
 
 // Number of tile-shape variants of the matrix-vector kernels.
