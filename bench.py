@@ -542,10 +542,56 @@ def serving_section(log, seconds: float, warmup: float = 1.0, rate: float = 2000
     srv2.close()
     out["below_capacity"] = {k: v for k, v in below.items() if k != "workspace_budget_bytes"}
     log("serving below capacity: " + json.dumps({k: v for k, v in below.items() if k != "stats"}))
+    out["small_requests"] = small_request_latency(ops[:2], pools, Server, budget)
+    log("serving small requests: " + json.dumps(out["small_requests"]))
     for op in ops:
         op.close()
     log("serving: " + json.dumps({k: v for k, v in out.items() if k not in ("sampled_checks", "stats")}))
     return out
+
+
+def small_request_latency(ops, pools, Server, budget, reps=50):
+    """One-vector requests on the two small serving operators, one at a time:
+    the median latency of a direct call (launch + synchronize), of a replayed
+    HIP graph of the same call, and of a server round trip (submit + wait on
+    an idle server, measured by the client), beside the GPU time of the
+    call's three kernels.  The difference is launch and notification
+    overhead."""
+    import statistics
+
+    import torch
+    rows = []
+    srv = Server(workspace_budget=budget, n_slots=4, max_batch_rhs=64)
+    for i, op in enumerate(ops):
+        for adj in (0, 1):
+            x = pools[i, adj][0][:1]
+            y = torch.empty((1, op.Nt, op.Nm if adj else op.Nd), dtype=torch.float64, device=x.device)
+            fn = op.rmatvec if adj else op.matvec
+            fn(x, out=y)
+            op.profile(True)
+            for _ in range(10):
+                fn(x, out=y)
+            torch.cuda.synchronize()
+            gpu_us = sum(op.profile_read()["adj" if adj else "fwd"]) * 1e3
+            op.profile(False)
+
+            def med(call):
+                lat = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    call()
+                    lat.append(time.perf_counter() - t0)
+                return round(statistics.median(lat) * 1e6, 1)
+
+            direct = med(lambda: (fn(x, out=y), torch.cuda.synchronize()))
+            g = op.graph(x, adjoint=bool(adj))
+            graph = med(lambda: (g.launch(), torch.cuda.synchronize()))
+            g.close()
+            server = med(lambda: srv.wait(srv.submit(op, x, adjoint=bool(adj), out=y)[0], timeout=60))
+            rows.append({"op": [op.Nt, op.Nd, op.Nm], "adjoint": adj, "kernels_us": round(gpu_us, 1),
+                         "direct_us": direct, "graph_us": graph, "server_us": server})
+    srv.close()
+    return {"workload": "1-vector FP32 requests, one at a time, median of " + str(reps), "rows": rows}
 
 
 def main() -> int:
