@@ -33,27 +33,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int GEMM_THREADS = 256;
+constexpr int GEMM_WAVES = GEMM_THREADS / 64;
 constexpr int FWD_BN = 64;   // spectrum rows per workgroup (forward)
 constexpr int ADJ_BN = 64;   // columns per workgroup (adjoint)
 constexpr int KC = 64;       // reals of K' per LDS chunk (forward)
 constexpr int LDS_PAD = 4;   // floats of padding per LDS row (bank spread)
 
-template <class T>
-__device__ __forceinline__ uint32_t to_bits16(float v);
-template <>
-__device__ __forceinline__ uint32_t to_bits16<__bf16>(float v) {
-  return __float_as_uint(v) >> 16;  // v is a bfloat16 value already: exact
-}
-template <>
-__device__ __forceinline__ uint32_t to_bits16<_Float16>(float v) {
-  return __half_as_ushort(__float2half_rn(v));  // exact for FP16 values
-}
-
 template <class S>
 struct MfmaOf;  // the 16x16x32 half-precision MFMA for a 16-bit storage format
 template <>
 struct MfmaOf<s_bf16> {
-  using half_t = __bf16;
   using vec = bf16x8;
   static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -61,7 +50,6 @@ struct MfmaOf<s_bf16> {
 };
 template <>
 struct MfmaOf<s_f16> {
-  using half_t = _Float16;
   using vec = f16x8;
   static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -216,14 +204,22 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
 }
 
 // ---------------------------------------------------------------------------
-// forward, FP16/BF16 storage: MFMA 16x16x32 (K' = 32 reals per instruction)
+// forward, FP16/BF16 storage: MFMA 16x16x32 (K' = 32 reals per instruction).
+// The input arrives in 16 bits in the product's format.  The product is
+// bound by its loads.  Each wave reads its 16 spectrum rows whole (16 lanes
+// per row, 256 contiguous bytes each) into its own LDS slab and takes the
+// MFMA operands from there: loads in the MFMA lane layout touch 64 bytes of
+// 16 rows per instruction and stream 25% slower (measured with a read-only
+// kernel: 4.9 vs 6.4 TB/s).
 // ---------------------------------------------------------------------------
-template <class S, int TB, class TX>
+constexpr int KCH = 128;  // reals of K' per LDS chunk (half-precision forward)
+
+template <class S, int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, int nbb, int nrb) {
   using M = MfmaOf<S>;
-  using H = typename M::half_t;
   constexpr int BM = 16 * TB;
-  __shared__ __align__(16) uint16_t xs[BM][KC + 8];  // X' in 16-bit, 64 reals per chunk
+  __shared__ __align__(16) uint16_t xs[BM][KCH + 8];             // X' chunk, 16-byte aligned rows
+  __shared__ __align__(16) uint16_t fsh[GEMM_WAVES][16][KCH + 8];  // each wave's spectrum rows
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t per_k = (int64_t)nbb * nrb;
   const int64_t k = wg / per_k;
@@ -233,65 +229,57 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
   const int kr = 2 * a.ld;
 
-  // X' is float32, or 16-bit values of the product's format (TX = h16)
-  const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + 2 * k * a.x_k_stride;
+  const uint16_t* __restrict__ X = reinterpret_cast<const uint16_t*>(a.x) + 2 * k * a.x_k_stride;
   const int64_t xrow = 2 * a.x_rhs_stride;
   const uint16_t* __restrict__ Fk = reinterpret_cast<const uint16_t*>(a.F) + 2 * k * a.f_k_stride;
-  const int r_me = min(r0 + l16, a.Nd - 1);
-  const uint16_t* __restrict__ frow = Fk + (int64_t)r_me * kr;
+  // load i of a chunk: row 4 i + lane / 16 of the wave's 16, reals 8 (lane mod 16) .. +7
+  constexpr int NF = 16 * KCH / (64 * 8);  // 16-byte loads per lane and chunk
+  const int f_row = lane >> 4, f_col = (lane & 15) * 8;
+  const uint16_t* __restrict__ frow[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) frow[i] = Fk + (int64_t)min(r0 + 4 * i + f_row, a.Nd - 1) * kr + f_col;
 
   f32x4 re[TB], im[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) re[t] = im[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  // X' staging: float4 e (of 16 BM per chunk) goes to row e / 16, reals
-  // 4 (e mod 16) .. +3, so 16 threads read one row's 256 B.  Chunk kc + KC is
-  // loaded into registers while the matrix cores work on chunk kc.
+  // X' staging: 16-byte piece e (of 16 per row) goes to row e / 16, reals
+  // 8 (e mod 16) .. +7, so 16 threads read one row's 256 B.  Chunk kc + KCH
+  // is loaded into registers while the matrix cores work on chunk kc.
   int st_row[TB], st_col[TB];
-  const TX* __restrict__ xsrc[TB];
+  const uint16_t* __restrict__ xsrc[TB];
 #pragma unroll
   for (int q = 0; q < TB; ++q) {
     const int e = threadIdx.x + GEMM_THREADS * q;
     st_row[q] = e >> 4;
-    st_col[q] = (e & 15) * 4;
+    st_col[q] = (e & 15) * 8;
     xsrc[q] = X + min(b0 + st_row[q], a.nrhs - 1) * xrow;
   }
-  using XV = typename std::conditional<std::is_same<TX, h16>::value, uint2, float4>::type;  // 4 reals
-  XV xv[TB];
-  uint4 fn[2];
+  constexpr int NS = KCH / 32;  // 32-real MFMA steps per chunk
+  uint4 xv[TB], fn[NF];
   auto load_chunk = [&](int kc) {
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
       const int col = kc + st_col[q];
-      xv[q] = col < kr ? *reinterpret_cast<const XV*>(xsrc[q] + col) : XV{};
+      xv[q] = col < kr ? *reinterpret_cast<const uint4*>(xsrc[q] + col) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int col = kc + 32 * s + 8 * g;
-      fn[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
-    }
+    for (int i = 0; i < NF; ++i)
+      fn[i] = kc + f_col < kr ? load_stream(frow[i] + kc) : make_uint4(0u, 0u, 0u, 0u);
   };
   load_chunk(0);
-  for (int kc = 0; kc < kr; kc += KC) {
+  for (int kc = 0; kc < kr; kc += KCH) {
 #pragma unroll
-    for (int q = 0; q < TB; ++q) {
-      uint16_t* d = &xs[st_row[q]][st_col[q]];
-      if constexpr (std::is_same<TX, h16>::value) {
-        *reinterpret_cast<uint2*>(d) = xv[q];  // already the product's 16-bit values
-      } else {
-        d[0] = (uint16_t)to_bits16<H>(xv[q].x);
-        d[1] = (uint16_t)to_bits16<H>(xv[q].y);
-        d[2] = (uint16_t)to_bits16<H>(xv[q].z);
-        d[3] = (uint16_t)to_bits16<H>(xv[q].w);
-      }
-    }
-    uint4 fv[2] = {fn[0], fn[1]};
+    for (int q = 0; q < TB; ++q) *reinterpret_cast<uint4*>(&xs[st_row[q]][st_col[q]]) = xv[q];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) *reinterpret_cast<uint4*>(&fsh[w][4 * i + f_row][f_col]) = fn[i];
     __syncthreads();
-    if (kc + KC < kr) load_chunk(kc + KC);
+    if (kc + KCH < kr) load_chunk(kc + KCH);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NS; ++s) {
       // each 32-bit word is (re | im << 16): Fr' flips the sign of im, Fi' swaps
-      const uint32_t u[4] = {fv[s].x, fv[s].y, fv[s].z, fv[s].w};
+      const uint4 fv = *reinterpret_cast<const uint4*>(&fsh[w][l16][32 * s + 8 * g]);
+      const uint32_t u[4] = {fv.x, fv.y, fv.z, fv.w};
       uint4 ur, ui;
       uint32_t* pr = reinterpret_cast<uint32_t*>(&ur);
       uint32_t* pi = reinterpret_cast<uint32_t*>(&ui);
@@ -529,13 +517,16 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
     }
 }
 
-// FP16/BF16 storage: MFMA 16x16x32, one k-step of 32 sensors per chunk.
-template <class S, int TB, class TX>
+// FP16/BF16 storage: MFMA 16x16x32, one k-step of 32 sensors per chunk.  The
+// data arrive in 16 bits in the product's format; each thread loads 4 sensors
+// of one right-hand side per 16-byte load.  (Tiles of 128 columns, which halve
+// the data tile's reads from L2, need more registers and measured slower.)
+template <class S, int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, int nbb, int ncb) {
   using M = MfmaOf<S>;
-  using H = typename M::half_t;
-  constexpr int BM = 16 * TB, NX = BM * RC / GEMM_THREADS;  // data-tile loads per thread
-  __shared__ uint32_t fs[RC][ADJ_BN + 4];            // (re | im << 16) per complex
+  constexpr int BM = 16 * TB, NXE = BM * RC / 4;             // 16-byte pieces of the data tile
+  constexpr int NX = (NXE + GEMM_THREADS - 1) / GEMM_THREADS;  // per thread
+  __shared__ uint32_t fs[RC][ADJ_BN + 4];                      // (re | im << 16) per complex
   __shared__ __align__(16) uint16_t xr16[BM][RC + 8];
   __shared__ __align__(16) uint16_t xi16[BM][RC + 8];
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
@@ -546,7 +537,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, c0 = cb * ADJ_BN;
 
-  const cplx<TX>* __restrict__ X = reinterpret_cast<const cplx<TX>*>(a.x) + k * a.x_k_stride;
+  const uint32_t* __restrict__ X = reinterpret_cast<const uint32_t*>(a.x) + k * a.x_k_stride;  // (re | im << 16)
   const uint32_t* __restrict__ Fk = reinterpret_cast<const uint32_t*>(a.F) + k * a.f_k_stride;
 
   f32x4 re[TB], im[TB];
@@ -556,8 +547,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   // Sensor chunk r0 + RC is loaded into registers while the matrix cores work
   // on chunk r0: the spectrum tile (32 rows x 64 columns, four complex per
   // 16-byte load) and the data tile (BM right-hand sides x 32 sensors).
-  uint4 fv[2];
-  cplx<TX> xv[NX];
+  uint4 fv[2], xv[NX];
   auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -569,9 +559,18 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
-      const int bl = idx >> 5, rr = idx & 31;
+      if (NXE % GEMM_THREADS != 0 && idx >= NXE) break;
+      const int bl = idx >> 3, rr = (idx & 7) * 4;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
-      xv[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<TX>{};
+      // 4 sensors r .. r + 3 (the row's length is a multiple of 8); those past Nd are zero
+      uint4 v = r < a.Nd ? *reinterpret_cast<const uint4*>(X + (int64_t)b * a.x_rhs_stride + r)
+                         : make_uint4(0u, 0u, 0u, 0u);
+      if (r + 3 >= a.Nd) {
+        v.y = r + 1 < a.Nd ? v.y : 0u;
+        v.z = r + 2 < a.Nd ? v.z : 0u;
+        v.w = r + 3 < a.Nd ? v.w : 0u;
+      }
+      xv[q] = v;
     }
   };
   load_chunk(0);
@@ -588,14 +587,13 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
-      const int bl = idx >> 5, rr = idx & 31;
-      if constexpr (std::is_same<TX, h16>::value) {
-        xr16[bl][rr] = xv[q].x.b;  // already the product's 16-bit values
-        xi16[bl][rr] = xv[q].y.b;
-      } else {
-        xr16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].x);  // exact: x holds values of the 16-bit format
-        xi16[bl][rr] = (uint16_t)to_bits16<H>(xv[q].y);
-      }
+      if (NXE % GEMM_THREADS != 0 && idx >= NXE) break;
+      const int bl = idx >> 3, rr = (idx & 7) * 4;
+      const uint4 v = xv[q];  // (re | im << 16) of 4 sensors: split into the two planes
+      *reinterpret_cast<uint2*>(&xr16[bl][rr]) =
+          make_uint2((v.x & 0xffffu) | (v.y << 16), (v.z & 0xffffu) | (v.w << 16));
+      *reinterpret_cast<uint2*>(&xi16[bl][rr]) =
+          make_uint2((v.x >> 16) | (v.y & 0xffff0000u), (v.z >> 16) | (v.w & 0xffff0000u));
     }
     __syncthreads();
     if (r0 + RC < a.Nd) load_chunk(r0 + RC);
@@ -817,31 +815,51 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_a64_kernel(GemvArgs a, 
 #pragma unroll
   for (int t = 0; t < TB; ++t) re[t] = im[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
-  // X' staging, two reals per thread and step: BM rows x KC64 reals
+  // X' staging, two reals per thread and step: BM rows x KC64 reals.  Chunk
+  // kc + KC64 (spectrum and X') is loaded into registers while the matrix
+  // cores work on chunk kc.
   constexpr int NPAIR = BM * KC64 / 2, NST = (NPAIR + GEMM_THREADS - 1) / GEMM_THREADS;
-  for (int kc = 0; kc < kr; kc += KC64) {
+  double2 xv[NST];
+  uint4 fn[4];
+  auto load_chunk = [&](int kc) {
 #pragma unroll
     for (int q = 0; q < NST; ++q) {
       const int e = threadIdx.x + GEMM_THREADS * q;
       if (NPAIR % GEMM_THREADS != 0 && e >= NPAIR) continue;
       const int row = e / (KC64 / 2), col = 2 * (e % (KC64 / 2));
       const TX* src = X + min(b0 + row, a.nrhs - 1) * xrow + kc + col;
-      double v0 = 0.0, v1 = 0.0;
+      xv[q] = make_double2(0.0, 0.0);
       if (kc + col < kr) {
-        v0 = (double)src[0];
-        v1 = (double)src[1];
+        if constexpr (sizeof(TX) == 8) {
+          xv[q] = *reinterpret_cast<const double2*>(src);
+        } else {
+          const float2 f = *reinterpret_cast<const float2*>(src);
+          xv[q] = make_double2((double)f.x, (double)f.y);
+        }
       }
-      xs[row][col] = v0;
-      xs[row][col + 1] = v1;
     }
     // this wave's spectrum rows: lane (l16, g) holds reals kc + RPL (4 s + g) ..
-    uint4 fv[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int col = kc + RPL * (4 * s + g);
-      fv[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+      fn[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
     }
+  };
+  load_chunk(0);
+  for (int kc = 0; kc < kr; kc += KC64) {
+#pragma unroll
+    for (int q = 0; q < NST; ++q) {
+      const int e = threadIdx.x + GEMM_THREADS * q;
+      if (NPAIR % GEMM_THREADS != 0 && e >= NPAIR) continue;
+      const int row = e / (KC64 / 2), col = 2 * (e % (KC64 / 2));
+      xs[row][col] = xv[q].x;
+      xs[row][col + 1] = xv[q].y;
+    }
+    uint4 fv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) fv[s] = fn[s];
     __syncthreads();
+    if (kc + KC64 < kr) load_chunk(kc + KC64);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       double f[RPL];
@@ -906,30 +924,44 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_a64_kernel(GemvArgs a, 
 #pragma unroll
   for (int t = 0; t < TB; ++t) re[t] = im[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
+  // Sensor chunk r0 + RC64 is loaded into registers while the matrix cores
+  // work on chunk r0: the spectrum tile RC64 x 64 (one complex per thread and
+  // step, coalesced rows) and the data tile BM x RC64 (sensors past Nd are zero).
   constexpr int NF = RC64 * ADJ_BN / GEMM_THREADS, NX = (BM * RC64 + GEMM_THREADS - 1) / GEMM_THREADS;
-  for (int r0 = 0; r0 < a.Nd; r0 += RC64) {
-    // spectrum tile RC64 x 64 (one complex per thread and step, coalesced rows)
+  cplx<TF> fn[NF];
+  cplx<TX> xn[NX];
+  auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int row = idx / ADJ_BN, col = idx % ADJ_BN;
       const int r = r0 + row, c = c0 + col;
-      cplx<TF> f = {(TF)0, (TF)0};
-      if (r < a.Nd && c < a.ld) f = Fk[(int64_t)r * a.ld + c];
-      fs[row][col] = {(double)f.x, (double)f.y};
+      fn[q] = (r < a.Nd && c < a.ld) ? Fk[(int64_t)r * a.ld + c] : cplx<TF>{(TF)0, (TF)0};
     }
-    // data tile BM right-hand sides x RC64 sensors (sensors past Nd are zero)
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       if ((BM * RC64) % GEMM_THREADS != 0 && idx >= BM * RC64) continue;
       const int bl = idx / RC64, rr = idx % RC64;
       const int b = min(b0 + bl, a.nrhs - 1), r = r0 + rr;
-      cplx<TX> x = {(TX)0, (TX)0};
-      if (r < a.Nd) x = X[(int64_t)b * a.x_rhs_stride + r];
-      xs[bl][rr] = {(double)x.x, (double)x.y};
+      xn[q] = r < a.Nd ? X[(int64_t)b * a.x_rhs_stride + r] : cplx<TX>{(TX)0, (TX)0};
+    }
+  };
+  load_chunk(0);
+  for (int r0 = 0; r0 < a.Nd; r0 += RC64) {
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      fs[idx / ADJ_BN][idx % ADJ_BN] = {(double)fn[q].x, (double)fn[q].y};
+    }
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int idx = tid + GEMM_THREADS * q;
+      if ((BM * RC64) % GEMM_THREADS != 0 && idx >= BM * RC64) continue;
+      xs[idx / RC64][idx % RC64] = {(double)xn[q].x, (double)xn[q].y};
     }
     __syncthreads();
+    if (r0 + RC64 < a.Nd) load_chunk(r0 + RC64);
 #pragma unroll
     for (int s = 0; s < RC64 / 4; ++s) {
       const cplx<double> f = fs[4 * s + g][w * 16 + l16];
@@ -988,12 +1020,12 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
   switch (fdt) {
     case DT_F32: hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB>), grid, block, 0, st, a, nbb, nrb); break;
     case DT_F16:
-      if (a.x16) hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB, h16>), grid, block, 0, st, a, nbb, nrb);
-      else hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB, float>), grid, block, 0, st, a, nbb, nrb);
+      if (!a.x16) return hipErrorInvalidValue;  // the input of a 16-bit product is stored in 16 bits
+      hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, nrb);
       break;
     case DT_BF16:
-      if (a.x16) hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB, h16>), grid, block, 0, st, a, nbb, nrb);
-      else hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB, float>), grid, block, 0, st, a, nbb, nrb);
+      if (!a.x16) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((gemm_fwd_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, nrb);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1013,12 +1045,12 @@ static hipError_t gemm_adj_go(int fdt, const GemvArgs& a, hipStream_t st) {
       else hipLaunchKernelGGL((gemm_adj_f32_kernel<TB>), grid, block, 0, st, a, nbb, ncb);
       break;
     case DT_F16:
-      if (a.x16) hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB, h16>), grid, block, 0, st, a, nbb, ncb);
-      else hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB, float>), grid, block, 0, st, a, nbb, ncb);
+      if (!a.x16) return hipErrorInvalidValue;  // the input of a 16-bit product is stored in 16 bits
+      hipLaunchKernelGGL((gemm_adj_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, ncb);
       break;
     case DT_BF16:
-      if (a.x16) hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB, h16>), grid, block, 0, st, a, nbb, ncb);
-      else hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB, float>), grid, block, 0, st, a, nbb, ncb);
+      if (!a.x16) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((gemm_adj_h_kernel<s_bf16, TB>), grid, block, 0, st, a, nbb, ncb);
       break;
     default: return hipErrorInvalidValue;
   }
