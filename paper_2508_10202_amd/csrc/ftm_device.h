@@ -105,6 +105,12 @@ __device__ __forceinline__ cplx<T> round_as(cplx<T> a, int dt) {
   return {round_as<HALF>(a.x, dt), round_as<HALF>(a.y, dt)};
 }
 
+// Format of a second rounding that follows one into `first`: rounding into
+// the same format again cannot change the value, so it becomes DT_F64, which
+// round_to and round_as treat as no rounding (a uniform value: the rounding
+// is skipped by a scalar branch).
+__device__ __forceinline__ int then_round(int first, int second) { return second == first ? DT_F64 : second; }
+
 // ---------------------------------------------------------------------------
 // 16-bit storage of a transformed vector between two phases, in FP16 or BF16
 // (the format is a launch argument).  Only values exact in that format are

@@ -179,6 +179,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     const int64_t xstep = (int64_t)rstep * a.x_row_stride;
     TC* comp = reinterpret_cast<TC*>(lds) + (j & 1);
     const int zb = (j >> 1) * N;
+    const int r_fft2 = then_round(a.r_pad, a.r_fft);
     for (int t = r0; t < Nt; t += FFT_LOAD_BATCH * rstep) {
       const double* q = xs + (int64_t)t * a.x_row_stride;
       double v[FFT_LOAD_BATCH];
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
 #pragma unroll
       for (int u = 0; u < FFT_LOAD_BATCH; ++u)
         if (t + u * rstep < Nt)
-          comp[2 * lds_ix(zb + t + u * rstep)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), a.r_fft);
+          comp[2 * lds_ix(zb + t + u * rstep)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), r_fft2);
     }
   }
   __syncthreads();
@@ -206,12 +207,13 @@ __global__ __launch_bounds__(TH) void rfft_pad_kernel(RfftArgs a, FftPlan plan,
     const int64_t ostep = (int64_t)rstep * a.out_k_stride;
     const int zb = (j >> 1) * N;
     const bool odd = j & 1;
+    const int r_next2 = then_round(a.r_fft, a.r_next);
     for (int k = r0; k < K; k += rstep, o += ostep) {
       const cplx<TC> zk = lds[lds_ix(zb + k)], zr = lds[lds_ix(zb + (k == 0 ? 0 : N - k))];
       cplx<TC> X;
       if (!odd) X = {(TC)0.5 * (zk.x + zr.x), (TC)0.5 * (zk.y - zr.y)};
       else X = {(TC)0.5 * (zk.y + zr.y), (TC)0.5 * (zr.x - zk.x)};
-      X = round_as<HALF>(round_as<HALF>(X, a.r_fft), a.r_next);
+      X = round_as<HALF>(round_as<HALF>(X, a.r_fft), r_next2);
       *o = to_store<TO>(X, a.r_next);  // one 16/8/4-byte store (16-bit: exact in format r_next)
     }
   }
@@ -298,11 +300,12 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
   const int64_t ystep = (int64_t)tstep * a.y_row_stride;
   const int zb = (j >> 1) * N;
   const bool odd = j & 1;
+  const int r_unpad2 = then_round(a.r_ifft, a.r_unpad);
   for (int t = t0; t < Nt; t += tstep, y += ystep) {
     const cplx<TC> z = lds[lds_ix(zb + t)];  // conj of N * (a_t + i b_t)
     TC v = (odd ? -z.y : z.x) * inv_n;
     v = round_as<HALF>(v, a.r_ifft);
-    *y = round_as<HALF>((double)v, a.r_unpad);
+    *y = round_as<HALF>((double)v, r_unpad2);
   }
 }
 

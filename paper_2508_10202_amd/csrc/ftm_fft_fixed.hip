@@ -184,7 +184,7 @@ __device__ __forceinline__ void rfft_first(cplx<TC>* lds, int Nt, int lane) {
 }
 
 // Bin k of both real series from Z_k and Z_{N-k}, rounded to the FFT format
-// and then to the next phase's: X = (Z_k + conj Z_{N-k}) / 2 goes to the
+// and then to r_next (the next phase's, or DT_F64 when that is the same): X = (Z_k + conj Z_{N-k}) / 2 goes to the
 // slot of element k, Y = (Z_k - conj Z_{N-k}) / 2i to that of N/2 + 1 + k.
 template <bool HALF, class TC>
 __device__ __forceinline__ void sep_bin(cplx<TC>* lds, int slot_x, int slot_y, cplx<TC> zk, cplx<TC> zr, int r_fft,
@@ -292,6 +292,7 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
     const double* xs = xb + off;
     TC* comp = reinterpret_cast<TC*>(slabs + (c / 2) * SL) + (c & 1);
     constexpr int U = 16;  // loads in flight per thread (a whole tile for most shapes)
+    const int r_fft2 = then_round(a.r_pad, a.r_fft);
     for (int t0 = t_first; t0 < Nt; t0 += U * t_step) {
       double v[U];
 #pragma unroll
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int t = t0 + u * t_step;
-        if (t < Nt) comp[2 * lds_ix(t)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), a.r_fft);
+        if (t < Nt) comp[2 * lds_ix(t)] = (TC)round_as<HALF>(round_as<HALF>(v[u], a.r_pad), r_fft2);
       }
     }
   }
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
     cplx<TC>* lds = slabs + slot * SL;
     rfft_first<P, T>(lds, Nt, lane);
     mid_passes<P, 1, T>(lds, lane, tw);
-    rfft_last<P, T, HALF>(lds, lane, tw, a.r_fft, a.r_next);
+    rfft_last<P, T, HALF>(lds, lane, tw, a.r_fft, then_round(a.r_fft, a.r_next));
   }
   __syncthreads();
   // tile store: bins k <= N/2 of column c; columns S .. pad_to-1 of the last
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
     cplx<TC>* lds = slabs + slot * SL;
     irfft_first<P, T>(lds, lane);
     mid_passes<P, 1, T>(lds, lane, tw);
-    irfft_last<P, T, HALF>(lds, Nt, lane, tw, a.r_ifft, a.r_unpad);
+    irfft_last<P, T, HALF>(lds, Nt, lane, tw, a.r_ifft, then_round(a.r_ifft, a.r_unpad));
   }
   __syncthreads();
   // tile store: rows t < Nt of column c
