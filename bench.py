@@ -182,11 +182,12 @@ PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 
 
-def multi_rhs_section(log):
+def multi_rhs_section(log, products_only=False):
     """64 right-hand sides at Nt=512, Nd=128, Nm=4096: the per-frequency product
     on the matrix cores (FP32 and BF16 storage, FP32 accumulation) against 64
     separate float64 matvecs on the same GPU; four right-hand sides are checked
-    against the oracle."""
+    against the oracle.  Then the nrhs sweep and the Hessian assembly, unless
+    `products_only`."""
     import torch
 
     import oracle
@@ -247,9 +248,10 @@ def multi_rhs_section(log):
                          "speedup_vs_fp64_separate": round(base / sum(kms), 2)}
         out[prec] = rec
         log(f"multi-rhs {prec}: " + json.dumps(rec))
-    out["nrhs_sweep"] = {prec: nrhs_sweep(op, s, Mt, Dt, prec) for prec in ("ddsdd", "ddddd")}
-    log("multi-rhs nrhs sweep: " + json.dumps(out["nrhs_sweep"]))
-    out["hessian"] = hessian_section(log, op, F, s, "Nt=512 Nd=128 Nm=4096")
+    if not products_only:
+        out["nrhs_sweep"] = {prec: nrhs_sweep(op, s, Mt, Dt, prec) for prec in ("ddsdd", "ddddd")}
+        log("multi-rhs nrhs sweep: " + json.dumps(out["nrhs_sweep"]))
+        out["hessian"] = hessian_section(log, op, F, s, "Nt=512 Nd=128 Nm=4096")
     op.close()
     return out
 
@@ -610,6 +612,9 @@ def main() -> int:
                          "so HBM byte counters can be scaled against a plain copy of known size")
     ap.add_argument("--no-multi-rhs", action="store_true",
                     help="skip the 64-right-hand-side GEMM measurement (Nt=512, Nd=128, Nm=4096)")
+    ap.add_argument("--multi-rhs-products-only", action="store_true",
+                    help="of the many-right-hand-side sections run only the 64-vector products at "
+                         "Nt=512, Nd=128, Nm=4096 (no nrhs sweeps, Hessian or standalone SBGEMV): for profiler runs")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="measured duration of the serving run (after a 1 s warm-up); 0 skips it")
     ap.add_argument("--serving-budget-gib", type=float, default=16.0,
@@ -736,7 +741,7 @@ def main() -> int:
         mixed = mixed_section(log, op, s, mt, dt, dout, mout, ref_d, ref_m, confs)
 
     paper_multi = None
-    if not args.no_multi_rhs:
+    if not args.no_multi_rhs and not args.multi_rhs_products_only:
         # many right-hand sides and the data-space Hessian at the paper's shape
         g = torch.Generator(device=dev)
         g.manual_seed(2508_10202 + 100 * 2 + 3)
@@ -747,8 +752,8 @@ def main() -> int:
         del M64, D64
         paper_multi["hessian"] = hessian_section(log, op, F, s, "Nt=1000 Nd=100 Nm=5000")
         op.set_precision(fwd="ddddd", adj="ddddd")
-    multi = None if args.no_multi_rhs else multi_rhs_section(log)
-    sbg = None if args.no_multi_rhs else sbgemv_section(log)
+    multi = None if args.no_multi_rhs else multi_rhs_section(log, args.multi_rhs_products_only)
+    sbg = None if args.no_multi_rhs or args.multi_rhs_products_only else sbgemv_section(log)
     serving = None
     if args.serving_seconds > 0:
         op.close()

@@ -99,22 +99,57 @@ __device__ __forceinline__ void tsync() {
   }
 }
 
+// Twiddles of pass S for this thread's butterflies, held in registers.  For
+// lengths of 1024 and more they are loaded one pass ahead (the first
+// twiddled pass's during the tile load), so that no pass waits for its
+// twiddles' global loads: there the slabs limit a workgroup to 4 waves per
+// SIMD, which leaves the registers free (64-right-hand-side transforms at
+// length 1024: 3-8% faster).  Shorter transforms run more waves, which the
+// extra registers would cost, and load each pass's twiddles just before it.
+template <class P>
+constexpr bool tw_ahead() { return P::N >= 1024; }
+
+// get(i, j, q): twiddle q of butterfly j = lane + i T of pass S.
+template <class P, int S, int T, class TC, bool AHEAD = tw_ahead<P>()>
+struct TwMid {  // registers, filled by load()
+  static constexpr int R = P::rad[S], NS = P::ns(S), nb = P::N / R, MB = (nb + T - 1) / T;
+  cplx<TC> w[MB][R];  // w[i][0] unused
+  __device__ __forceinline__ void load(const cplx<TC>* __restrict__ tw, int lane) {
+    const cplx<TC>* tws = tw + P::toff(S);
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const int j = lane + i * T;
+      if (nb % T == 0 || j < nb) {
+        const int jm = NS == nb ? j : j % NS;
+#pragma unroll
+        for (int q = 1; q < R; ++q) w[i][q] = tws[jm * R + q];
+      }
+    }
+  }
+  __device__ __forceinline__ cplx<TC> get(int i, int, int q) const { return w[i][q]; }
+};
+template <class P, int S, int T, class TC>
+struct TwMid<P, S, T, TC, false> {  // loaded where the pass uses them
+  static constexpr int R = P::rad[S], NS = P::ns(S), nb = P::N / R;
+  const cplx<TC>* tws;
+  __device__ __forceinline__ void load(const cplx<TC>* __restrict__ tw, int) { tws = tw + P::toff(S); }
+  __device__ __forceinline__ cplx<TC> get(int, int j, int q) const { return tws[(NS == nb ? j : j % NS) * R + q]; }
+};
+
 // A middle pass S of plan P: butterfly j = lane + i T < N/R reads points
 // j + q N/R, twiddles them, and writes its DFT to (j - jm) R + jm + q Ns with
 // jm = j mod Ns.  All reads precede all writes (the pass works in place).
 template <class P, int S, int T, class TC>
-__device__ __forceinline__ void mid_pass(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw) {
+__device__ __forceinline__ void mid_pass(cplx<TC>* lds, int lane, const TwMid<P, S, T, TC>& tw) {
   constexpr int R = P::rad[S], NS = P::ns(S), nb = P::N / R, MB = (nb + T - 1) / T;
-  const cplx<TC>* tws = tw + P::toff(S);
   cplx<TC> v[MB][R];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int j = lane + i * T;
     if (nb % T == 0 || j < nb) {
-      const int jm = j % NS;
       v[i][0] = lds[lds_ix(j)];
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_at<nb>(j, q)], tws[jm * R + q]);
+      for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_at<nb>(j, q)], tw.get(i, j, q));
     }
   }
   tsync<T>();
@@ -131,13 +166,6 @@ __device__ __forceinline__ void mid_pass(cplx<TC>* lds, int lane, const cplx<TC>
   tsync<T>();
 }
 
-template <class P, int S, int T, class TC>
-__device__ __forceinline__ void mid_passes(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw) {
-  if constexpr (S + 1 < P::nst) {
-    mid_pass<P, S, T>(lds, lane, tw);
-    mid_passes<P, S + 1, T>(lds, lane, tw);
-  }
-}
 
 // Paired passes (a pass with nb = N/R butterflies whose outputs or inputs are
 // needed in conjugate pairs) run in units u < (nb + 1) / 2: unit 0 holds
@@ -198,12 +226,44 @@ __device__ __forceinline__ void sep_bin(cplx<TC>* lds, int slot_x, int slot_y, c
 // Last pass (Ns = nb, so jm = j) in paired units; the separated bins
 // k <= N/2 of both series replace the transform in its slab.  All reads
 // precede all writes.
+// Twiddles of the forward transform's last pass in paired units: get1 / get2
+// give twiddle q of butterflies j1 and j2 of unit lane + i T.
+template <class P, int T, class TC, bool AHEAD = tw_ahead<P>()>
+struct TwLast {
+  static constexpr int S = P::nst - 1, R = P::rad[S], nb = P::N / R, nu = (nb + 1) / 2, MU = (nu + T - 1) / T;
+  cplx<TC> w1[MU][R], w2[MU][R];  // [.][0] unused
+  __device__ __forceinline__ cplx<TC> get1(int i, int, int q) const { return w1[i][q]; }
+  __device__ __forceinline__ cplx<TC> get2(int i, int, int q) const { return w2[i][q]; }
+  __device__ __forceinline__ void load(const cplx<TC>* __restrict__ tw, int lane) {
+    const cplx<TC>* tws = tw + P::toff(S);
+#pragma unroll
+    for (int i = 0; i < MU; ++i) {
+      const int u = lane + i * T;
+      if (nu % T != 0 && u >= nu) continue;
+      const int j1 = u, j2 = partner_butterfly<nb>(u);
+#pragma unroll
+      for (int q = 1; q < R; ++q) w1[i][q] = tws[j1 * R + q];
+      if (has_second<nb>(u)) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) w2[i][q] = tws[j2 * R + q];
+      }
+    }
+  }
+};
+template <class P, int T, class TC>
+struct TwLast<P, T, TC, false> {
+  static constexpr int S = P::nst - 1, R = P::rad[S];
+  const cplx<TC>* tws;
+  __device__ __forceinline__ void load(const cplx<TC>* __restrict__ tw, int) { tws = tw + P::toff(S); }
+  __device__ __forceinline__ cplx<TC> get1(int, int j1, int q) const { return tws[j1 * R + q]; }
+  __device__ __forceinline__ cplx<TC> get2(int, int j2, int q) const { return tws[j2 * R + q]; }
+};
+
 template <class P, int T, bool HALF, class TC>
-__device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw, int r_fft,
+__device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const TwLast<P, T, TC>& tw, int r_fft,
                                           int r_next) {
   constexpr int S = P::nst - 1, R = P::rad[S], N = P::N, nb = N / R, nu = (nb + 1) / 2, hN = N / 2;
   constexpr int MU = (nu + T - 1) / T;
-  const cplx<TC>* tws = tw + P::toff(S);
   cplx<TC> v1[MU][R], v2[MU][R];
 #pragma unroll
   for (int i = 0; i < MU; ++i) {
@@ -212,11 +272,11 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
     const int j1 = u, j2 = partner_butterfly<nb>(u);
     v1[i][0] = lds[lds_ix(j1)];
 #pragma unroll
-    for (int q = 1; q < R; ++q) v1[i][q] = cmul(lds[lds_at<nb>(j1, q)], tws[j1 * R + q]);
+    for (int q = 1; q < R; ++q) v1[i][q] = cmul(lds[lds_at<nb>(j1, q)], tw.get1(i, j1, q));
     if (has_second<nb>(u)) {
       v2[i][0] = lds[lds_ix(j2)];
 #pragma unroll
-      for (int q = 1; q < R; ++q) v2[i][q] = cmul(lds[lds_at<nb>(j2, q)], tws[j2 * R + q]);
+      for (int q = 1; q < R; ++q) v2[i][q] = cmul(lds[lds_at<nb>(j2, q)], tw.get2(i, j2, q));
     }
   }
   tsync<T>();
@@ -253,6 +313,25 @@ __device__ __forceinline__ void rfft_last(cplx<TC>* lds, int lane, const cplx<TC
   }
 }
 
+// Passes S .. nst-1 of the forward transform; w holds pass S's twiddles and
+// pass S + 1's are loaded before pass S runs.
+template <class P, int S, int T, class TC>
+using RfftTw = typename std::conditional<S == P::nst - 1, TwLast<P, T, TC>, TwMid<P, S, T, TC>>::type;
+
+template <class P, int S, int T, bool HALF, class TC>
+__device__ __forceinline__ void rfft_passes(cplx<TC>* lds, int lane, const cplx<TC>* __restrict__ tw,
+                                            const RfftTw<P, S, T, TC>& w, int r_fft, int r_next) {
+  if constexpr (S == P::nst - 1) {
+    rfft_last<P, T, HALF>(lds, lane, w, r_fft, r_next);
+  } else {
+    RfftTw<P, S + 1, T, TC> wn;
+    if constexpr (tw_ahead<P>()) wn.load(tw, lane);
+    mid_pass<P, S, T>(lds, lane, w);
+    if constexpr (!tw_ahead<P>()) wn.load(tw, lane);
+    rfft_passes<P, S + 1, T, HALF>(lds, lane, tw, wn, r_fft, r_next);
+  }
+}
+
 // Slab of transform `slot`: N + 2 complex values (the separated bins of both
 // series need N + 2), rounded up to 16, plus 2, so that consecutive slabs
 // start 4 (float) or 8 (float64) banks apart: the lanes of a tile load or
@@ -267,9 +346,12 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
   constexpr int N = P::N, WG = C / 2 * T, SL = slab_size<N>(), ROWS = WG / C;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<TC>* slabs = reinterpret_cast<cplx<TC>*>(smem_raw);
+  static_assert(P::nst >= 2, "a fixed plan has at least two passes");
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t b = wg / ntile, s0 = (wg - b * ntile) * C;
   const int tid = threadIdx.x, Nt = a.Nt;
+  RfftTw<P, 1, T, TC> w1;  // the first twiddled pass's, in flight during the tile load
+  if constexpr (tw_ahead<P>()) w1.load(tw, tid % T);
 
   // tile load: thread tid takes column c = tid mod C of rows tid / C + n ROWS
   // (row-contiguous input), or, when time is the contiguous axis (a setup
@@ -312,8 +394,8 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
     const int slot = tid / T, lane = tid % T;
     cplx<TC>* lds = slabs + slot * SL;
     rfft_first<P, T>(lds, Nt, lane);
-    mid_passes<P, 1, T>(lds, lane, tw);
-    rfft_last<P, T, HALF>(lds, lane, tw, a.r_fft, then_round(a.r_fft, a.r_next));
+    if constexpr (!tw_ahead<P>()) w1.load(tw, lane);
+    rfft_passes<P, 1, T, HALF>(lds, lane, tw, w1, a.r_fft, then_round(a.r_fft, a.r_next));
   }
   __syncthreads();
   // tile store: bins k <= N/2 of column c; columns S .. pad_to-1 of the last
@@ -440,10 +522,9 @@ __device__ __forceinline__ void irfft_first(cplx<TC>* lds, int lane) {
 // (series s as the real part, s + 1 as the imaginary part of slot t).  All
 // reads precede all writes.
 template <class P, int T, bool HALF, class TC>
-__device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, const cplx<TC>* __restrict__ tw,
+__device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, const TwMid<P, P::nst - 1, T, TC>& tw,
                                            int r_ifft, int r_unpad) {
   constexpr int S = P::nst - 1, R = P::rad[S], N = P::N, nb = N / R, MB = (nb + T - 1) / T;
-  const cplx<TC>* tws = tw + P::toff(S);
   const TC inv_n = (TC)(1.0 / (double)N);
   cplx<TC> v[MB][R];
 #pragma unroll
@@ -452,7 +533,7 @@ __device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, cons
     if ((nb % T != 0 && j >= nb) || j >= Nt) continue;
     v[i][0] = lds[lds_ix(j)];
 #pragma unroll
-    for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_at<nb>(j, q)], tws[j * R + q]);
+    for (int q = 1; q < R; ++q) v[i][q] = cmul(lds[lds_at<nb>(j, q)], tw.get(i, j, q));  // jm = j
   }
   tsync<T>();
 #pragma unroll
@@ -471,6 +552,22 @@ __device__ __forceinline__ void irfft_last(cplx<TC>* lds, int Nt, int lane, cons
   }
 }
 
+// Passes S .. nst-1 of the inverse transform, with the twiddles of each pass
+// loaded one pass ahead as in the forward transform.
+template <class P, int S, int T, bool HALF, class TC>
+__device__ __forceinline__ void irfft_passes(cplx<TC>* lds, int Nt, int lane, const cplx<TC>* __restrict__ tw,
+                                             const TwMid<P, S, T, TC>& w, int r_ifft, int r_unpad) {
+  if constexpr (S == P::nst - 1) {
+    irfft_last<P, T, HALF>(lds, Nt, lane, w, r_ifft, r_unpad);
+  } else {
+    TwMid<P, S + 1, T, TC> wn;
+    if constexpr (tw_ahead<P>()) wn.load(tw, lane);
+    mid_pass<P, S, T>(lds, lane, w);
+    if constexpr (!tw_ahead<P>()) wn.load(tw, lane);
+    irfft_passes<P, S + 1, T, HALF>(lds, Nt, lane, tw, wn, r_ifft, r_unpad);
+  }
+}
+
 template <class P, class TI, class TC, bool HALF, int T, int C>
 __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, const cplx<TC>* __restrict__ tw,
                                                                 int64_t ntile) {
@@ -480,6 +577,9 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
   const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
   const int64_t b = wg / ntile, s0 = (wg - b * ntile) * C;
   const int tid = threadIdx.x, Nt = a.Nt;
+  static_assert(P::nst >= 2, "a fixed plan has at least two passes");
+  TwMid<P, 1, T, TC> w1;  // the first twiddled pass's, in flight during the tile load
+  if constexpr (tw_ahead<P>()) w1.load(tw, tid % T);
 
   // tile load of bins k <= N/2, rounded to the IFFT format; the imaginary
   // parts of bins 0 and N/2 are dropped, as a real inverse transform does
@@ -512,8 +612,8 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
     const int slot = tid / T, lane = tid % T;
     cplx<TC>* lds = slabs + slot * SL;
     irfft_first<P, T>(lds, lane);
-    mid_passes<P, 1, T>(lds, lane, tw);
-    irfft_last<P, T, HALF>(lds, Nt, lane, tw, a.r_ifft, then_round(a.r_ifft, a.r_unpad));
+    if constexpr (!tw_ahead<P>()) w1.load(tw, lane);
+    irfft_passes<P, 1, T, HALF>(lds, Nt, lane, tw, w1, a.r_ifft, then_round(a.r_ifft, a.r_unpad));
   }
   __syncthreads();
   // tile store: rows t < Nt of column c
