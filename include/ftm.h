@@ -250,7 +250,8 @@ ftm_status ftm_select_precision(ftm_operator op, int32_t adjoint, double toleran
  *   fft_shape[d][i]   transform kernel of direction d, i = 0 the input
  *                     transform (phases 1-2), 1 the output one (4-5): 0 the
  *                     default (the larger tile unless it gives fewer than 4
- *                     tiles per CU, then the smaller), 1 / 2 the fixed-plan
+ *                     tiles per CU or needs more than half of a CU's LDS,
+ *                     then the smaller), 1 / 2 the fixed-plan
  *                     kernels' larger / smaller column tile (lengths that
  *                     have them: 128, 256, 400, 512, 1024, 2000; others run
  *                     the runtime-plan kernels whatever the value), 3 the

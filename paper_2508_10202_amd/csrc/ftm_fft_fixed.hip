@@ -704,10 +704,19 @@ bool same_plan(const FftPlan& plan) {
 
 bool is_half(int dt) { return dt == DT_F16 || dt == DT_BF16; }
 
-// Whether the larger tile gives fewer than 4 tiles per CU (256 CUs).
-bool few_tiles(int64_t S, int nrhs, bool tc64) {
-  const int C = tc64 ? tile_columns<double>(1) : tile_columns<float>(1);
-  return (S + C - 1) / C * nrhs < 4 * 256;
+// Whether the smaller tile is the default: when the larger tile gives fewer
+// than 4 tiles per CU (256 CUs), or when its slabs take more than half of a
+// CU's 160 KB of LDS, so that one workgroup, which synchronises at every
+// pass, would run alone on each CU (length 2000: 64-right-hand-side inverse
+// transforms 3.3 -> 2.6 ms in float32).
+template <class TC>
+bool small_tile(int64_t S, int nrhs) {
+  constexpr int C = tile_columns<TC>(1);
+  constexpr size_t lds = (size_t)(C / 2) * slab_size<FTM_FIXED_N>() * sizeof(cplx<TC>);
+  return lds > 80 * 1024 || (S + C - 1) / C * nrhs < 4 * 256;
+}
+bool small_tile(int64_t S, int nrhs, bool tc64) {
+  return tc64 ? small_tile<double>(S, nrhs) : small_tile<float>(S, nrhs);
 }
 
 template <class TC, class TO, int SH>
@@ -759,7 +768,7 @@ hipError_t irfft_go(const IrfftArgs& a, const void* tw, hipStream_t st) {
 bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, int out_st, const RfftArgs& a, const FftPlan& plan,
                                                 const void* tw, int shape, hipStream_t st, hipError_t* err) {
   if (!(tc64 ? same_plan<PlanF64>(plan) : same_plan<PlanF32>(plan))) return false;
-  const bool alt = shape == 2 || (shape == 0 && few_tiles(a.S, a.nrhs, tc64));
+  const bool alt = shape == 2 || (shape == 0 && small_tile(a.S, a.nrhs, tc64));
 #define FTM_RGO(TC, TO) *err = alt ? rfft_go<TC, TO, 2>(a, tw, st) : rfft_go<TC, TO, 1>(a, tw, st)
   if (tc64) {
     if (out_st == ST_F64) FTM_RGO(double, double);
@@ -776,7 +785,7 @@ bool FTM_CAT(launch_rfft_fixed_, FTM_FIXED_N)(bool tc64, int out_st, const RfftA
 bool FTM_CAT(launch_irfft_fixed_, FTM_FIXED_N)(int in_st, bool tc64, const IrfftArgs& a, const FftPlan& plan,
                                                  const void* tw, int shape, hipStream_t st, hipError_t* err) {
   if (!(tc64 ? same_plan<PlanI64>(plan) : same_plan<PlanI32>(plan))) return false;
-  const bool alt = shape == 2 || (shape == 0 && few_tiles(a.S, a.nrhs, tc64));
+  const bool alt = shape == 2 || (shape == 0 && small_tile(a.S, a.nrhs, tc64));
 #define FTM_IGO(TI, TC) *err = alt ? irfft_go<TI, TC, 2>(a, tw, st) : irfft_go<TI, TC, 1>(a, tw, st)
   if (in_st == ST_16) return false;  // not a storage the inverse transform reads
   if (tc64) {
