@@ -39,10 +39,32 @@ constexpr int ADJ_BN = 64;   // columns per workgroup (adjoint)
 constexpr int KC = 64;       // reals of K' per LDS chunk (forward)
 constexpr int LDS_PAD = 4;   // floats of padding per LDS row (bank spread)
 
+// Rounding of a float value into a format fixed at compile time (DT_F32 and
+// DT_F64: none).  with_round(dt, f) calls f with the rounding into a format
+// known only at run time: dt is uniform, so one branch chooses the
+// instantiation and the caller's loop has none.
+template <int DT>
+struct RoundF {
+  __device__ __forceinline__ float operator()(float x) const {
+    if constexpr (DT == DT_F16) return round_f16(x);
+    else if constexpr (DT == DT_BF16) return round_bf16(x);
+    else return x;
+  }
+};
+template <class Fn>
+__device__ __forceinline__ void with_round(int dt, Fn&& f) {
+  switch (dt) {
+    case DT_F16: f(RoundF<DT_F16>{}); break;
+    case DT_BF16: f(RoundF<DT_BF16>{}); break;
+    default: f(RoundF<DT_F64>{}); break;
+  }
+}
+
 template <class S>
 struct MfmaOf;  // the 16x16x32 half-precision MFMA for a 16-bit storage format
 template <>
 struct MfmaOf<s_bf16> {
+  static constexpr int dt = DT_BF16;
   using vec = bf16x8;
   static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -50,17 +72,13 @@ struct MfmaOf<s_bf16> {
 };
 template <>
 struct MfmaOf<s_f16> {
+  static constexpr int dt = DT_F16;
   using vec = f16x8;
   static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
 };
 
-// one complex output, rounded to the product's format then the next phase's
-__device__ __forceinline__ void store_c(float* y, float re, float im, int r_gemv, int r_next) {
-  *reinterpret_cast<float2*>(y) = make_float2(round_to(round_to(re, r_gemv), r_next),
-                                              round_to(round_to(im, r_gemv), r_next));
-}
 
 // ---------------------------------------------------------------------------
 // FP32 products on the BF16 matrix cores.  An FP32 value splits exactly into
@@ -115,10 +133,10 @@ template <int NW, int TB>
 __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
   constexpr int TH = 64 * NW, BM = 16 * TB;
   __shared__ float xs[BM][KC + LDS_PAD];
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * nrb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * nrb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = (rb * NW + w) * 16;
@@ -191,16 +209,17 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
   const int r = r0 + l16;
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+  // FP32 values of the product, rounded into the next phase's format
+  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+    for (int t = 0; t < TB; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) {
-        float* y = Y + 2 * (b * a.y_rhs_stride + r);
-        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
+      for (int v = 0; v < 4; ++v) {
+        const int b = b0 + 16 * t + 4 * g + v;
+        if (b < a.nrhs)
+          *reinterpret_cast<float2*>(Y + 2 * (b * a.y_rhs_stride + r)) = make_float2(rnd(re[t][v]), rnd(im[t][v]));
       }
-    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -220,10 +239,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   constexpr int BM = 16 * TB;
   __shared__ __align__(16) uint16_t xs[BM][KCH + 8];             // X' chunk, 16-byte aligned rows
   __shared__ __align__(16) uint16_t fsh[GEMM_WAVES][16][KCH + 8];  // each wave's spectrum rows
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * nrb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * nrb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
@@ -303,13 +322,18 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   const int r = r0 + l16;
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+  // rounded into the product's format (that of S), then the next phase's
+  with_round(then_round(M::dt, a.r_next), [&](auto rnd) {
+    const RoundF<M::dt> rs;
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+    for (int t = 0; t < TB; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + r), re[t][v], im[t][v], a.r_gemv, a.r_next);
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int b = b0 + 16 * t + 4 * g + v;
+        if (b < a.nrhs)
+          *reinterpret_cast<float2*>(Y + 2 * (b * a.y_rhs_stride + r)) = make_float2(rnd(rs(re[t][v])), rnd(rs(im[t][v])));
+      }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -321,10 +345,10 @@ template <int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, int nbb, int nrb) {
   constexpr int BM = 16 * TB;
   __shared__ __align__(16) uint16_t xs[3][BM][KC + 8];  // X' terms, 64 reals per chunk
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * nrb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * nrb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
@@ -411,16 +435,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, i
   const int r = r0 + l16;
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+  // FP32 values of the product, rounded into the next phase's format
+  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+    for (int t = 0; t < TB; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) {
-        float* y = Y + 2 * (b * a.y_rhs_stride + r);
-        store_c(y, re[t][v], im[t][v], a.r_gemv, a.r_next);
+      for (int v = 0; v < 4; ++v) {
+        const int b = b0 + 16 * t + 4 * g + v;
+        if (b < a.nrhs)
+          *reinterpret_cast<float2*>(Y + 2 * (b * a.y_rhs_stride + r)) = make_float2(rnd(re[t][v]), rnd(im[t][v]));
       }
-    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -437,10 +462,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
   constexpr int BM = 16 * TB, NX = BM * RC / GEMM_THREADS;  // data-tile loads per thread
   __shared__ cplx<float> fs[RC][ADJ_BN + 2];
   __shared__ cplx<float> xs[BM][RC + 1];
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * ncb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * ncb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / ncb, cb = rem - bb * ncb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, c0 = cb * ADJ_BN;
@@ -508,13 +533,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
   const int c = c0 + w * 16 + l16;
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+  // FP32 values of the product, rounded into the next phase's format
+  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+    for (int t = 0; t < TB; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int b = b0 + 16 * t + 4 * g + v;
+        if (b < a.nrhs)
+          *reinterpret_cast<float2*>(Y + 2 * (b * a.y_rhs_stride + c)) = make_float2(rnd(re[t][v]), rnd(im[t][v]));
+      }
+  });
 }
 
 // FP16/BF16 storage: MFMA 16x16x32, one k-step of 32 sensors per chunk.  The
@@ -526,13 +555,13 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   using M = MfmaOf<S>;
   constexpr int BM = 16 * TB, NXE = BM * RC / 4;             // 16-byte pieces of the data tile
   constexpr int NX = (NXE + GEMM_THREADS - 1) / GEMM_THREADS;  // per thread
-  __shared__ uint32_t fs[RC][ADJ_BN + 4];                      // (re | im << 16) per complex
+  __shared__ __align__(16) uint32_t fs[RC][ADJ_BN + 4];        // (re | im << 16) per complex
   __shared__ __align__(16) uint16_t xr16[BM][RC + 8];
   __shared__ __align__(16) uint16_t xi16[BM][RC + 8];
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * ncb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * ncb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / ncb, cb = rem - bb * ncb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, c0 = cb * ADJ_BN;
@@ -579,10 +608,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
     for (int q = 0; q < 2; ++q) {
       const int idx = tid + GEMM_THREADS * q;
       const int row = idx >> 4, col = (idx & 15) * 4;
-      fs[row][col] = fv[q].x;
-      fs[row][col + 1] = fv[q].y;
-      fs[row][col + 2] = fv[q].z;
-      fs[row][col + 3] = fv[q].w;
+      *reinterpret_cast<uint4*>(&fs[row][col]) = fv[q];  // 16-byte aligned: rows of 68 words
     }
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
@@ -629,13 +655,18 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   const int c = c0 + w * 16 + l16;
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+  // rounded into the product's format (that of S), then the next phase's
+  with_round(then_round(M::dt, a.r_next), [&](auto rnd) {
+    const RoundF<M::dt> rs;
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+    for (int t = 0; t < TB; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int b = b0 + 16 * t + 4 * g + v;
+        if (b < a.nrhs)
+          *reinterpret_cast<float2*>(Y + 2 * (b * a.y_rhs_stride + c)) = make_float2(rnd(rs(re[t][v])), rnd(rs(im[t][v])));
+      }
+  });
 }
 
 // FP32 storage on the BF16 matrix cores (three-term split).  The spectrum
@@ -653,10 +684,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_x3_kernel(GemvArgs a, i
   __shared__ __align__(16) uint16_t fim[3][ADJ_BN][RP];
   __shared__ __align__(16) uint16_t xre[3][BM][RP];
   __shared__ __align__(16) uint16_t xim[3][BM][RP];
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * ncb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * ncb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / ncb, cb = rem - bb * ncb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, c0 = cb * ADJ_BN;
@@ -763,13 +794,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_x3_kernel(GemvArgs a, i
   const int c = c0 + w * 16 + l16;
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
+  // FP32 values of the product, rounded into the next phase's format
+  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+    for (int t = 0; t < TB; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + 16 * t + 4 * g + v;
-      if (b < a.nrhs) store_c(Y + 2 * (b * a.y_rhs_stride + c), re[t][v], im[t][v], a.r_gemv, a.r_next);
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int b = b0 + 16 * t + 4 * g + v;
+        if (b < a.nrhs)
+          *reinterpret_cast<float2*>(Y + 2 * (b * a.y_rhs_stride + c)) = make_float2(rnd(re[t][v]), rnd(im[t][v]));
+      }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -788,18 +823,19 @@ __device__ __forceinline__ void store_c64(double* y, double re, double im, int, 
   *reinterpret_cast<double2*>(y) = make_double2(re, im);
 }
 __device__ __forceinline__ void store_c64(float* y, double re, double im, int r_gemv, int r_next) {
-  *reinterpret_cast<float2*>(y) = make_float2((float)round_to(round_to(re, r_gemv), r_next),
-                                              (float)round_to(round_to(im, r_gemv), r_next));
+  const int r2 = then_round(r_gemv, r_next);
+  *reinterpret_cast<float2*>(y) = make_float2((float)round_to(round_to(re, r_gemv), r2),
+                                              (float)round_to(round_to(im, r_gemv), r2));
 }
 
 template <class TF, class TX, class TY, int TB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_a64_kernel(GemvArgs a, int nbb, int nrb) {
   constexpr int BM = 16 * TB, RPL = 16 / sizeof(TF), KC64 = 16 * RPL;  // reals per chunk
   __shared__ double xs[BM][KC64 + 2];
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * nrb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * nrb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
@@ -909,10 +945,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_a64_kernel(GemvArgs a, 
   constexpr int BM = 16 * TB;
   __shared__ cplx<double> fs[RC64][ADJ_BN + 1];
   __shared__ cplx<double> xs[BM][RC64 + 1];
-  const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-  const int64_t per_k = (int64_t)nbb * ncb;
-  const int64_t k = wg / per_k;
-  const int rem = (int)(wg - k * per_k);
+  const int wg = xcd_order(blockIdx.x, gridDim.x);  // grids stay below 2^31 workgroups
+  const int per_k = nbb * ncb;
+  const int k = wg / per_k;
+  const int rem = wg - k * per_k;
   const int bb = rem / ncb, cb = rem - bb * ncb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, c0 = cb * ADJ_BN;
@@ -1009,6 +1045,7 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
     const int nrb = (a.Nd + 16 * GEMM_FWD_NW - 1) / (16 * GEMM_FWD_NW);
     const int64_t nwg = (int64_t)a.K * nbb * nrb;
     if (nwg <= 0) return hipSuccess;
+    if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((gemm_fwd_f32_kernel<GEMM_FWD_NW, TB>), dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0, st, a,
                        nbb, nrb);
     return hipGetLastError();
@@ -1016,6 +1053,7 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
   const int nrb = (a.Nd + FWD_BN - 1) / FWD_BN;
   const int64_t nwg = (int64_t)a.K * nbb * nrb;
   if (nwg <= 0) return hipSuccess;
+  if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
     case DT_F32: hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB>), grid, block, 0, st, a, nbb, nrb); break;
@@ -1037,6 +1075,7 @@ static hipError_t gemm_adj_go(int fdt, const GemvArgs& a, hipStream_t st) {
   const int nbb = (a.nrhs + 16 * TB - 1) / (16 * TB), ncb = (a.Nm + ADJ_BN - 1) / ADJ_BN;
   const int64_t nwg = (int64_t)a.K * nbb * ncb;
   if (nwg <= 0) return hipSuccess;
+  if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
     case DT_F32:  // the split-term kernel by default at 64-RHS tiles with more than one sensor chunk
@@ -1063,6 +1102,7 @@ static hipError_t gemm_a64_go(bool adjoint, const GemvArgs& a, hipStream_t st) {
   const int nb2 = adjoint ? (a.Nm + ADJ_BN - 1) / ADJ_BN : (a.Nd + FWD_BN - 1) / FWD_BN;
   const int64_t nwg = (int64_t)a.K * nbb * nb2;
   if (nwg <= 0) return hipSuccess;
+  if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   if (adjoint) hipLaunchKernelGGL((gemm_adj_a64_kernel<TF, TX, TY, TB>), grid, block, 0, st, a, nbb, nb2);
   else hipLaunchKernelGGL((gemm_fwd_a64_kernel<TF, TX, TY, TB>), grid, block, 0, st, a, nbb, nb2);
