@@ -235,6 +235,37 @@ def test_fft_tiles_zero_the_padding_columns(gpu, shape):
     op.close()
 
 
+@pytest.mark.parametrize("s", [Shape(512, 3, 40, decay=200.0), Shape(1000, 3, 40, decay=300.0)])
+def test_long_transforms_every_tile_several_vectors(gpu, s):
+    """The fixed-plan transforms of lengths 1024 and 2000 (twiddles held in
+    registers one pass ahead) with 3 right-hand sides, in float64, float32 and
+    with BF16 rounding: each transform kernel matches the oracle, and the
+    larger and smaller column tiles give bitwise the same result (the tile
+    decides only which workgroup transforms a column)."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    F, M, D = make_F(s, 71), make_m(s, 72, nrhs=3), make_d(s, 73, nrhs=3)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s", "b"), max_rhs=3)
+    Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
+    want_d, want_m = oracle.forward(F, M), oracle.adjoint(F, D)
+    for prec in ("ddddd", "sssss", "dbbbd"):
+        op.set_precision(fwd=prec, adj=prec)
+        got = {}
+        for shape in (0, 1, 2):
+            op.set_tuning(fft_shape=((shape, shape), (shape, shape)))
+            got[shape] = (op.matvec(Mt).cpu().numpy(), op.rmatvec(Dt).cpu().numpy())
+            _say(f"case long transforms {s.Nt} {prec} tile {shape}")
+            e_f, e_a = _rel(got[shape][0], want_d), _rel(got[shape][1], want_m)
+            if prec == "ddddd":
+                assert e_f <= FP64_TOL and e_a <= FP64_TOL, (prec, shape, e_f, e_a)
+            else:
+                lo_f, hi_f = mp_bounds(prec, s.L, s.Nm)
+                lo_a, hi_a = mp_bounds(prec, s.L, s.Nd)
+                assert lo_f <= e_f <= hi_f and lo_a <= e_a <= hi_a, (prec, shape, e_f, e_a)
+        assert np.array_equal(got[1][0], got[2][0]) and np.array_equal(got[1][1], got[2][1]), prec
+    op.close()
+
+
 def test_apply_on_caller_workspaces_concurrently(gpu):
     """ftm_apply on two NaN-filled caller workspaces, on two streams at once:
     both results equal the operator's own-workspace call bitwise."""
