@@ -105,6 +105,56 @@ __device__ __forceinline__ cplx<T> round_as(cplx<T> a, int dt) {
   return {round_as<HALF>(a.x, dt), round_as<HALF>(a.y, dt)};
 }
 
+// Rounding into a format fixed at compile time: RoundInto<DT>{}(x) equals
+// round_to(x, DT) (DT_F64 rounds nothing; DT_F32 nothing for float values).
+template <int DT>
+struct RoundInto {
+  __device__ __forceinline__ float operator()(float x) const { return round_to(x, DT); }
+  __device__ __forceinline__ double operator()(double x) const { return round_to(x, DT); }
+  template <class T>
+  __device__ __forceinline__ cplx<T> operator()(cplx<T> a) const {
+    return {(*this)(a.x), (*this)(a.y)};
+  }
+};
+// round_as<false> as a function object (no half format: a select at most).
+struct RoundNoHalf {
+  int dt;
+  __device__ __forceinline__ float operator()(float x) const { return round_as<false>(x, dt); }
+  __device__ __forceinline__ double operator()(double x) const { return round_as<false>(x, dt); }
+  template <class T>
+  __device__ __forceinline__ cplx<T> operator()(cplx<T> a) const {
+    return {(*this)(a.x), (*this)(a.y)};
+  }
+};
+// round_as<true> as a function object (a format switch per value).
+struct RoundAnyFormat {
+  int dt;
+  __device__ __forceinline__ float operator()(float x) const { return round_to(x, dt); }
+  __device__ __forceinline__ double operator()(double x) const { return round_to(x, dt); }
+  template <class T>
+  __device__ __forceinline__ cplx<T> operator()(cplx<T> a) const {
+    return {(*this)(a.x), (*this)(a.y)};
+  }
+};
+// with_round<T>(dt, f) calls f(RoundInto<dt>{}) for values of type T, with
+// the uniform format dt turned into a compile-time constant by one branch,
+// so that the caller's loop holds no per-value format switch.  For float
+// values DT_F32 and DT_F64 share one instantiation (no rounding).
+template <class T, class Fn>
+__device__ __forceinline__ void with_round(int dt, Fn&& f) {
+  switch (dt) {
+    case DT_F16: f(RoundInto<DT_F16>{}); break;
+    case DT_BF16: f(RoundInto<DT_BF16>{}); break;
+    case DT_F32:
+      if constexpr (std::is_same<T, double>::value) {
+        f(RoundInto<DT_F32>{});
+        break;
+      }
+      [[fallthrough]];
+    default: f(RoundInto<DT_F64>{}); break;
+  }
+}
+
 // Format of a second rounding that follows one into `first`: rounding into
 // the same format again cannot change the value, so it becomes DT_F64, which
 // round_to and round_as treat as no rounding (a uniform value: the rounding

@@ -39,27 +39,6 @@ constexpr int ADJ_BN = 64;   // columns per workgroup (adjoint)
 constexpr int KC = 64;       // reals of K' per LDS chunk (forward)
 constexpr int LDS_PAD = 4;   // floats of padding per LDS row (bank spread)
 
-// Rounding of a float value into a format fixed at compile time (DT_F32 and
-// DT_F64: none).  with_round(dt, f) calls f with the rounding into a format
-// known only at run time: dt is uniform, so one branch chooses the
-// instantiation and the caller's loop has none.
-template <int DT>
-struct RoundF {
-  __device__ __forceinline__ float operator()(float x) const {
-    if constexpr (DT == DT_F16) return round_f16(x);
-    else if constexpr (DT == DT_BF16) return round_bf16(x);
-    else return x;
-  }
-};
-template <class Fn>
-__device__ __forceinline__ void with_round(int dt, Fn&& f) {
-  switch (dt) {
-    case DT_F16: f(RoundF<DT_F16>{}); break;
-    case DT_BF16: f(RoundF<DT_BF16>{}); break;
-    default: f(RoundF<DT_F64>{}); break;
-  }
-}
-
 template <class S>
 struct MfmaOf;  // the 16x16x32 half-precision MFMA for a 16-bit storage format
 template <>
@@ -210,7 +189,7 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
   // FP32 values of the product, rounded into the next phase's format
-  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
+  with_round<float>(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -323,8 +302,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
   // rounded into the product's format (that of S), then the next phase's
-  with_round(then_round(M::dt, a.r_next), [&](auto rnd) {
-    const RoundF<M::dt> rs;
+  with_round<float>(then_round(M::dt, a.r_next), [&](auto rnd) {
+    const RoundInto<M::dt> rs;
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -436,7 +415,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, i
   if (r >= a.Nd) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
   // FP32 values of the product, rounded into the next phase's format
-  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
+  with_round<float>(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -534,7 +513,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_f32_kernel(GemvArgs a, 
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
   // FP32 values of the product, rounded into the next phase's format
-  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
+  with_round<float>(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -656,8 +635,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_h_kernel(GemvArgs a, in
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
   // rounded into the product's format (that of S), then the next phase's
-  with_round(then_round(M::dt, a.r_next), [&](auto rnd) {
-    const RoundF<M::dt> rs;
+  with_round<float>(then_round(M::dt, a.r_next), [&](auto rnd) {
+    const RoundInto<M::dt> rs;
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
@@ -795,7 +774,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_adj_x3_kernel(GemvArgs a, i
   if (c >= a.Nm) return;
   float* Y = reinterpret_cast<float*>(a.y) + 2 * k * a.y_k_stride;
   // FP32 values of the product, rounded into the next phase's format
-  with_round(then_round(DT_F32, a.r_next), [&](auto rnd) {
+  with_round<float>(then_round(DT_F32, a.r_next), [&](auto rnd) {
 #pragma unroll
     for (int t = 0; t < TB; ++t)
 #pragma unroll
