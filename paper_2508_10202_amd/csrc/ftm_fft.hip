@@ -278,7 +278,7 @@ __global__ __launch_bounds__(TH) void irfft_unpad_kernel(IrfftArgs a, FftPlan pl
       for (int u = 0; u < FFT_LOAD_BATCH; ++u) {
         const int kk = k + u * kstep;
         if (kk >= K) continue;
-        cplx<TC> Au = round_as<HALF>(A[u], a.r_ifft), Bu = round_as<HALF>(B[u], a.r_ifft);
+        cplx<TC> Au = A[u], Bu = B[u];  // already in the IFFT format: the product's epilogue rounded them
         if (kk == 0 || kk == hN) {
           Au.y = (TC)0;
           Bu.y = (TC)0;

@@ -615,8 +615,9 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
   TwMid<P, 1, T, TC> w1;  // the first twiddled pass's, in flight during the tile load
   if constexpr (tw_ahead<P>()) w1.load(tw, tid % T);
 
-  // tile load of bins k <= N/2, rounded to the IFFT format; the imaginary
-  // parts of bins 0 and N/2 are dropped, as a real inverse transform does
+  // tile load of bins k <= N/2, which the product's epilogue already rounded
+  // into the IFFT format (its next phase's); the imaginary parts of bins 0
+  // and N/2 are dropped, as a real inverse transform does
   {
     const int c = tid % C;
     const bool live = s0 + c < a.S;
@@ -635,7 +636,7 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
       for (int u = 0; u < U; ++u) {
         const int k = k0 + u * ROWS;
         if (k > hN) continue;
-        cplx<TC> z = round_as<HALF>(cplx<TC>{(TC)v[u].x, (TC)v[u].y}, a.r_ifft);
+        cplx<TC> z = {(TC)v[u].x, (TC)v[u].y};
         if (k == 0 || k == hN) z.y = (TC)0;
         slab[lds_ix(off + k)] = z;
       }

@@ -94,7 +94,7 @@ struct IrfftArgs {
   double* y;
   double* const* yptr;  // optional per-right-hand-side output pointers
   int64_t y_rhs_stride, y_row_stride;
-  int r_ifft, r_unpad;
+  int r_ifft, r_unpad;  // formats of the outputs (the input arrives rounded into r_ifft by the product)
 };
 
 // Phase 3: per-frequency product with the stored spectrum F[k][r][c]
