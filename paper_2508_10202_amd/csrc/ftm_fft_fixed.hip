@@ -109,12 +109,14 @@ __device__ __forceinline__ void tsync() {
 template <class P>
 constexpr bool tw_ahead() { return P::N >= 1024; }
 
-// Kernels with half-precision rounding turn the launch's uniform formats
-// into compile-time constants at each rounding site (one branch per thread,
-// no format switch per value: 64-right-hand-side forward transforms at
-// length 1024 with BF16 rounding 15-18% faster) for lengths of 1024 and more;
-// shorter transforms would lose occupancy to the extra code paths'
-// registers and switch per value.
+// Forward transforms with half-precision rounding turn the launch's uniform
+// formats into compile-time constants where they round (the bin separation,
+// and the tile load when the pad phase is float64): one branch per thread
+// instead of a format switch per value (64-right-hand-side forward
+// transforms at length 1024 with BF16 rounding 15-18% faster).  Only for
+// lengths of 1024 and more: shorter transforms would lose occupancy to the
+// extra code paths' registers.  The inverse transforms, less bound by their
+// vector instructions, gained nothing from it and keep the switch.
 template <class P, bool HALF>
 constexpr bool fixed_formats() { return HALF && P::N >= 1024; }
 
