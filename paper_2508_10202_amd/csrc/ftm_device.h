@@ -40,19 +40,15 @@ __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y
 // Round-to-nearest-even into the storage formats, branch free.
 //   float -> FP16: the hardware conversion (round to nearest even, subnormal
 //   results kept, overflow to infinity) and back.
-//   float -> BF16: BF16 is the top half of a float; adding 0x7fff plus the
-//   lowest kept bit to the bits and truncating rounds to nearest even
-//   (carries into the exponent give the next binade or infinity); NaN is kept.
+//   float -> BF16: the hardware conversion (v_cvt_pk_bf16_f32: round to
+//   nearest even, subnormal results kept, overflow to infinity, NaN stays
+//   NaN) and back (BF16 is the top half of a float).
 //   double -> FP16/BF16: round to odd into float first (truncate, then set the
 //   last bit if anything was dropped), then to nearest even: with float's 24
 //   bits at least two more than the target's, the two steps give the direct
 //   rounding (Boldo and Melquiond, IEEE TC 2008).
 __device__ __forceinline__ float round_f16(float x) { return __half2float(__float2half_rn(x)); }
-__device__ __forceinline__ float round_bf16(float x) {
-  const uint32_t u = __float_as_uint(x);
-  const float r = __uint_as_float((u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u);
-  return x != x ? x : r;
-}
+__device__ __forceinline__ float round_bf16(float x) { return (float)(__bf16)x; }
 __device__ __forceinline__ float to_float_odd(double x) {
   const float f = (float)x;
   const double df = (double)f;
