@@ -418,7 +418,34 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
     const double* xs = xb + off;
     TC* comp = reinterpret_cast<TC*>(slabs + (c / 2) * SL) + (c & 1);
     constexpr int U = 16;  // loads in flight per thread (a whole tile for most shapes)
+    // whole tiles of contiguous columns on 16-byte aligned rows: columns 2j
+    // and 2j + 1 are the real and imaginary parts of transform j, so one
+    // 16-byte load fills a slot of its slab (float32 transforms: 64-vector
+    // transforms 21-24% faster; float64 ones measured 2% slower with it)
+    constexpr bool can_pair = std::is_same<TC, float>::value;
+    const bool paired = can_pair && !tmajor && a.x_sc == 1 && a.ncol >= a.S && s0 + C <= a.S &&
+                        (a.x_row_stride & 1) == 0 && (reinterpret_cast<uintptr_t>(xb + s0) & 15) == 0;
     auto load_tile = [&](auto r_pad, auto r_fft) {
+      if (can_pair && paired) {
+        constexpr int PR = WG / (C / 2), UP = U / 2;  // rows per pass, loads in flight
+        const int j = tid % (C / 2);
+        const double* xp = xb + s0 + 2 * j;
+        cplx<TC>* slab = slabs + j * SL;
+        for (int t0 = tid / (C / 2); t0 < Nt; t0 += UP * PR) {
+          double2 v[UP];
+#pragma unroll
+          for (int u = 0; u < UP; ++u) {
+            const int t = t0 + u * PR;
+            v[u] = t < Nt ? *reinterpret_cast<const double2*>(xp + (int64_t)t * a.x_row_stride) : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < UP; ++u) {
+            const int t = t0 + u * PR;
+            if (t < Nt) slab[lds_ix(t)] = {(TC)r_fft(r_pad(v[u].x)), (TC)r_fft(r_pad(v[u].y))};
+          }
+        }
+        return;
+      }
       for (int t0 = t_first; t0 < Nt; t0 += U * t_step) {
         double v[U];
 #pragma unroll
@@ -691,11 +718,25 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
   __syncthreads();
   // tile store: rows t < Nt of column c
   {
+    double* yb = a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride;
+    // whole tiles on 16-byte aligned rows: one 16-byte store writes a slot of
+    // slab j, time step t of columns 2j and 2j + 1
+    if (s0 + C <= a.S && (a.y_row_stride & 1) == 0 && (reinterpret_cast<uintptr_t>(yb + s0) & 15) == 0) {
+      constexpr int PR = WG / (C / 2);  // rows per pass
+      const int j = tid % (C / 2);
+      const cplx<TC>* slab = slabs + j * SL;
+      double* yp = yb + s0 + 2 * j;
+      for (int t = tid / (C / 2); t < Nt; t += PR) {
+        const cplx<TC> z = slab[lds_ix(t)];
+        *reinterpret_cast<double2*>(yp + (int64_t)t * a.y_row_stride) = make_double2((double)z.x, (double)z.y);
+      }
+      return;
+    }
     const int c = tid % C;
     const int64_t s = s0 + c;
     if (s >= a.S) return;
     const TC* src = reinterpret_cast<const TC*>(slabs + (c / 2) * SL) + (c & 1);
-    double* y = (a.yptr ? a.yptr[b] : a.y + b * a.y_rhs_stride) + s;
+    double* y = yb + s;
     for (int t = tid / C; t < Nt; t += ROWS) y[(int64_t)t * a.y_row_stride] = (double)src[2 * lds_ix(t)];
   }
 }

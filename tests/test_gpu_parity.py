@@ -266,6 +266,36 @@ def test_long_transforms_every_tile_several_vectors(gpu, s):
     op.close()
 
 
+def test_unaligned_vectors_match_aligned(gpu):
+    """Input and output vectors 8 bytes past a 16-byte boundary take the
+    transforms' per-column loads and stores, while whole tiles of aligned
+    rows take the 16-byte loads and stores of column pairs: both give bitwise
+    the same result, in float64, float32 and with BF16 rounding."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(512, 16, 48)
+    F, M, D = make_F(s, 81), make_m(s, 82, nrhs=2), make_d(s, 83, nrhs=2)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s", "b"), max_rhs=2)
+    Mt, Dt = torch.from_numpy(M).cuda(), torch.from_numpy(D).cuda()
+
+    def shifted(a):
+        buf = torch.empty(a.numel() + 1, dtype=torch.float64, device="cuda")
+        v = buf[1:].view(a.shape)
+        v.copy_(a)
+        assert v.data_ptr() % 16 == 8
+        return v
+
+    for prec in ("ddddd", "sssss", "dbbbd"):
+        _say(f"case unaligned vectors {prec}")
+        op.set_precision(fwd=prec, adj=prec)
+        want_d, want_m = op.matvec(Mt), op.rmatvec(Dt)
+        out_d, out_m = shifted(torch.zeros_like(want_d)), shifted(torch.zeros_like(want_m))
+        op.matvec(shifted(Mt), out=out_d)
+        op.rmatvec(shifted(Dt), out=out_m)
+        assert torch.equal(out_d, want_d) and torch.equal(out_m, want_m), prec
+    op.close()
+
+
 def test_apply_on_caller_workspaces_concurrently(gpu):
     """ftm_apply on two NaN-filled caller workspaces, on two streams at once:
     both results equal the operator's own-workspace call bitwise."""
