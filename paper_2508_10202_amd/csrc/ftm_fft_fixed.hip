@@ -494,6 +494,23 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
   // tile are the padding the products read (times the spectrum's zero
   // padding) and are written as zeros
   {
+    if constexpr (std::is_same<TO, float>::value) {
+      // float32 output, a whole tile of live columns on 16-byte aligned rows:
+      // one 16-byte store writes bin k of columns 2j and 2j + 1
+      cplx<float>* ob = reinterpret_cast<cplx<float>*>(a.out) + b * a.out_rhs_stride + s0;
+      if (s0 + C <= a.S && a.ncol >= a.S && (a.out_k_stride & 1) == 0 &&
+          (reinterpret_cast<uintptr_t>(ob) & 15) == 0) {
+        constexpr int PR = WG / (C / 2);  // rows per pass
+        const int j = tid % (C / 2);
+        const cplx<TC>* slab = slabs + j * SL;
+        for (int k = tid / (C / 2); k <= N / 2; k += PR) {
+          const cplx<TC> z0 = slab[lds_ix(k)], z1 = slab[lds_ix(N / 2 + 1 + k)];
+          *reinterpret_cast<float4*>(ob + 2 * j + (int64_t)k * a.out_k_stride) =
+              make_float4((float)z0.x, (float)z0.y, (float)z1.x, (float)z1.y);
+        }
+        return;
+      }
+    }
     const int c = tid % C;
     const int64_t s = s0 + c;
     if (s >= a.S && s >= a.pad_to) return;
@@ -683,13 +700,44 @@ __global__ __launch_bounds__(C / 2 * T) void irfft_fixed_kernel(IrfftArgs a, con
   // tile load of bins k <= N/2, which the product's epilogue already rounded
   // into the IFFT format (its next phase's); the imaginary parts of bins 0
   // and N/2 are dropped, as a real inverse transform does
-  {
+  bool loaded = false;
+  constexpr int U = 16;
+  if constexpr (std::is_same<TI, float>::value) {
+    // float32 input, a whole tile on 16-byte aligned rows: one 16-byte load
+    // gives bin k of columns 2j and 2j + 1
+    const cplx<float>* ib = reinterpret_cast<const cplx<float>*>(a.in) + b * a.in_rhs_stride + s0;
+    if (s0 + C <= a.S && (a.in_k_stride & 1) == 0 && (reinterpret_cast<uintptr_t>(ib) & 15) == 0) {
+      constexpr int PR = WG / (C / 2), UP = U / 2;  // rows per pass, loads in flight
+      const int j = tid % (C / 2);
+      cplx<TC>* slab = slabs + j * SL;
+      const cplx<float>* ip = ib + 2 * j;
+      for (int k0 = tid / (C / 2); k0 <= hN; k0 += UP * PR) {
+        float4 v[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          const int k = k0 + u * PR;
+          v[u] = k <= hN ? *reinterpret_cast<const float4*>(ip + (int64_t)k * a.in_k_stride)
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          const int k = k0 + u * PR;
+          if (k > hN) continue;
+          cplx<TC> z0 = {(TC)v[u].x, (TC)v[u].y}, z1 = {(TC)v[u].z, (TC)v[u].w};
+          if (k == 0 || k == hN) z0.y = z1.y = (TC)0;
+          slab[lds_ix(k)] = z0;
+          slab[lds_ix(hN + 1 + k)] = z1;
+        }
+      }
+      loaded = true;
+    }
+  }
+  if (!loaded) {
     const int c = tid % C;
     const bool live = s0 + c < a.S;
     const cplx<TI>* in = reinterpret_cast<const cplx<TI>*>(a.in) + b * a.in_rhs_stride + (live ? s0 + c : 0);
     cplx<TC>* slab = slabs + (c / 2) * SL;
     const int off = (c & 1) ? hN + 1 : 0;
-    constexpr int U = 16;
     for (int k0 = tid / C; k0 <= hN; k0 += U * ROWS) {
       cplx<TI> v[U];
 #pragma unroll
