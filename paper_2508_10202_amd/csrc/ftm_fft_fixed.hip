@@ -494,19 +494,27 @@ __global__ __launch_bounds__(C / 2 * T) void rfft_fixed_kernel(RfftArgs a, const
   // tile are the padding the products read (times the spectrum's zero
   // padding) and are written as zeros
   {
-    if constexpr (std::is_same<TO, float>::value) {
-      // float32 output, a whole tile of live columns on 16-byte aligned rows:
-      // one 16-byte store writes bin k of columns 2j and 2j + 1
-      cplx<float>* ob = reinterpret_cast<cplx<float>*>(a.out) + b * a.out_rhs_stride + s0;
+    if constexpr (!std::is_same<TO, double>::value) {
+      // float32 or 16-bit output, a whole tile of live columns on rows
+      // aligned to a pair: one 16- or 8-byte store writes bin k of columns 2j
+      // and 2j + 1
+      cplx<TO>* ob = reinterpret_cast<cplx<TO>*>(a.out) + b * a.out_rhs_stride + s0;
+      constexpr uintptr_t PB = 2 * sizeof(cplx<TO>);  // bytes of a pair
       if (s0 + C <= a.S && a.ncol >= a.S && (a.out_k_stride & 1) == 0 &&
-          (reinterpret_cast<uintptr_t>(ob) & 15) == 0) {
+          (reinterpret_cast<uintptr_t>(ob) & (PB - 1)) == 0) {
         constexpr int PR = WG / (C / 2);  // rows per pass
         const int j = tid % (C / 2);
         const cplx<TC>* slab = slabs + j * SL;
         for (int k = tid / (C / 2); k <= N / 2; k += PR) {
           const cplx<TC> z0 = slab[lds_ix(k)], z1 = slab[lds_ix(N / 2 + 1 + k)];
-          *reinterpret_cast<float4*>(ob + 2 * j + (int64_t)k * a.out_k_stride) =
-              make_float4((float)z0.x, (float)z0.y, (float)z1.x, (float)z1.y);
+          cplx<TO>* o = ob + 2 * j + (int64_t)k * a.out_k_stride;
+          if constexpr (std::is_same<TO, float>::value) {
+            *reinterpret_cast<float4*>(o) = make_float4((float)z0.x, (float)z0.y, (float)z1.x, (float)z1.y);
+          } else {  // 16 bits, exact in format r_next
+            const cplx<h16> h0 = to_store<h16>(z0, a.r_next), h1 = to_store<h16>(z1, a.r_next);
+            *reinterpret_cast<uint2*>(o) = make_uint2(h0.x.b | ((uint32_t)h0.y.b << 16),
+                                                      h1.x.b | ((uint32_t)h1.y.b << 16));
+          }
         }
         return;
       }
