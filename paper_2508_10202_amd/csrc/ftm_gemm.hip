@@ -108,7 +108,7 @@ __device__ __forceinline__ f32x4 mma_split(const bf16x8 (&a)[3], const bf16x8 (&
 constexpr int GEMM_FWD_NW = FTM_GEMM_FWD_NW;
 
 
-template <int NW, int TB>
+template <int NW, int TB, bool SKIP>
 __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int nbb, int nrb) {
   constexpr int TH = 64 * NW, BM = 16 * TB;
   __shared__ float xs[BM][KC + LDS_PAD];
@@ -119,6 +119,11 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = (rb * NW + w) * 16;
+  // waves whose 16 rows all lie past Nd only stage X' for the others (their
+  // products would be discarded): no spectrum loads, no matrix-core work.
+  // Only with SKIP (at least half the waves idle): the branch costs this
+  // kernel registers, and with them a wave per SIMD
+  const bool rows_live = !SKIP || __builtin_amdgcn_readfirstlane(r0) < a.Nd;
   const int kr = 2 * a.ld;  // reals per row
 
   const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
@@ -161,23 +166,25 @@ __global__ __launch_bounds__(64 * NW) void gemm_fwd_f32_kernel(GemvArgs a, int n
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int col = kc + 16 * s + 4 * g;
-      fv[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+      fv[s] = rows_live && col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
+    if (rows_live) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float f0 = __uint_as_float(fv[s].x), f1 = __uint_as_float(fv[s].y);
-      const float f2 = __uint_as_float(fv[s].z), f3 = __uint_as_float(fv[s].w);
-      const float br[4] = {f0, -f1, f2, -f3};  // (re, -im, ..)
-      const float bi[4] = {f1, f0, f3, f2};    // (im, re, ..)
+      for (int s = 0; s < 4; ++s) {
+        const float f0 = __uint_as_float(fv[s].x), f1 = __uint_as_float(fv[s].y);
+        const float f2 = __uint_as_float(fv[s].z), f3 = __uint_as_float(fv[s].w);
+        const float br[4] = {f0, -f1, f2, -f3};  // (re, -im, ..)
+        const float bi[4] = {f1, f0, f3, f2};    // (im, re, ..)
 #pragma unroll
-      for (int t = 0; t < TB; ++t) {
-        const float4 xa = *reinterpret_cast<const float4*>(&xs[16 * t + l16][16 * s + 4 * g]);
-        const float av[4] = {xa.x, xa.y, xa.z, xa.w};
+        for (int t = 0; t < TB; ++t) {
+          const float4 xa = *reinterpret_cast<const float4*>(&xs[16 * t + l16][16 * s + 4 * g]);
+          const float av[4] = {xa.x, xa.y, xa.z, xa.w};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v], br[v], re[t], 0, 0, 0);
-          im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v], bi[v], im[t], 0, 0, 0);
+          for (int v = 0; v < 4; ++v) {
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v], br[v], re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[v], bi[v], im[t], 0, 0, 0);
+          }
         }
       }
     }
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_h_kernel(GemvArgs a, in
 // tiling of the half-precision forward kernel; X' is staged in LDS as its
 // three BF16 terms, the spectrum values are split in registers.
 // ---------------------------------------------------------------------------
-template <int TB>
+template <int TB, bool SKIP>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, int nbb, int nrb) {
   constexpr int BM = 16 * TB;
   __shared__ __align__(16) uint16_t xs[3][BM][KC + 8];  // X' terms, 64 reals per chunk
@@ -331,6 +338,11 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, i
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
+  // waves whose 16 rows all lie past Nd only stage X' for the others (their
+  // products would be discarded): no spectrum loads, no matrix-core work.
+  // Only with SKIP (at least half the waves idle): the branch costs this
+  // kernel registers, and with them a wave per SIMD
+  const bool rows_live = !SKIP || __builtin_amdgcn_readfirstlane(r0) < a.Nd;
   const int kr = 2 * a.ld;
 
   const float* __restrict__ X = reinterpret_cast<const float*>(a.x) + 2 * k * a.x_k_stride;
@@ -365,7 +377,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, i
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int col = kc + 32 * (h >> 1) + 8 * g + 4 * (h & 1);
-      fn[h] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+      fn[h] = rows_live && col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
     }
   };
   load_chunk(0);
@@ -384,28 +396,30 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_x3_kernel(GemvArgs a, i
     uint4 fv[4] = {fn[0], fn[1], fn[2], fn[3]};
     __syncthreads();
     if (kc + KC < kr) load_chunk(kc + KC);
+    if (rows_live) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      // the 8 reals of this lane: (re, im) pairs; Fr' = (re, -im), Fi' = (im, re)
-      const uint32_t u[8] = {fv[2 * s].x, fv[2 * s].y, fv[2 * s].z, fv[2 * s].w,
-                             fv[2 * s + 1].x, fv[2 * s + 1].y, fv[2 * s + 1].z, fv[2 * s + 1].w};
-      bf16x8 br[3], bi[3];
+      for (int s = 0; s < 2; ++s) {
+        // the 8 reals of this lane: (re, im) pairs; Fr' = (re, -im), Fi' = (im, re)
+        const uint32_t u[8] = {fv[2 * s].x, fv[2 * s].y, fv[2 * s].z, fv[2 * s].w,
+                               fv[2 * s + 1].x, fv[2 * s + 1].y, fv[2 * s + 1].z, fv[2 * s + 1].w};
+        bf16x8 br[3], bi[3];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const Split3 sre = split3(__uint_as_float(u[2 * q])), sim = split3(__uint_as_float(u[2 * q + 1]));
+        for (int q = 0; q < 4; ++q) {
+          const Split3 sre = split3(__uint_as_float(u[2 * q])), sim = split3(__uint_as_float(u[2 * q + 1]));
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-          reinterpret_cast<uint32_t*>(&br[p])[q] = pack2(sre.h[p], sim.h[p] ^ 0x8000u);
-          reinterpret_cast<uint32_t*>(&bi[p])[q] = pack2(sim.h[p], sre.h[p]);
+          for (int p = 0; p < 3; ++p) {
+            reinterpret_cast<uint32_t*>(&br[p])[q] = pack2(sre.h[p], sim.h[p] ^ 0x8000u);
+            reinterpret_cast<uint32_t*>(&bi[p])[q] = pack2(sim.h[p], sre.h[p]);
+          }
         }
-      }
 #pragma unroll
-      for (int t = 0; t < TB; ++t) {
-        bf16x8 xa[3];
+        for (int t = 0; t < TB; ++t) {
+          bf16x8 xa[3];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) xa[p] = *reinterpret_cast<const bf16x8*>(&xs[p][16 * t + l16][32 * s + 8 * g]);
-        re[t] = mma_split(xa, br, re[t]);
-        im[t] = mma_split(xa, bi, im[t]);
+          for (int p = 0; p < 3; ++p) xa[p] = *reinterpret_cast<const bf16x8*>(&xs[p][16 * t + l16][32 * s + 8 * g]);
+          re[t] = mma_split(xa, br, re[t]);
+          im[t] = mma_split(xa, bi, im[t]);
+        }
       }
     }
     __syncthreads();
@@ -818,6 +832,9 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_a64_kernel(GemvArgs a, 
   const int bb = rem / nrb, rb = rem - bb * nrb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
   const int b0 = bb * BM, r0 = rb * FWD_BN + w * 16;
+  // waves whose 16 rows all lie past Nd only stage X' for the others (their
+  // products would be discarded): no spectrum loads, no matrix-core work
+  const bool rows_live = __builtin_amdgcn_readfirstlane(r0) < a.Nd;
   const int kr = 2 * a.ld;
 
   const TX* __restrict__ X = reinterpret_cast<const TX*>(a.x) + 2 * k * a.x_k_stride;
@@ -857,7 +874,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_a64_kernel(GemvArgs a, 
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int col = kc + RPL * (4 * s + g);
-      fn[s] = col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
+      fn[s] = rows_live && col < kr ? load_stream(frow + col) : make_uint4(0u, 0u, 0u, 0u);
     }
   };
   load_chunk(0);
@@ -875,29 +892,31 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_fwd_a64_kernel(GemvArgs a, 
     for (int s = 0; s < 4; ++s) fv[s] = fn[s];
     __syncthreads();
     if (kc + KC64 < kr) load_chunk(kc + KC64);
+    if (rows_live) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double f[RPL];
-      if constexpr (RPL == 2) {
-        const double2 d = __builtin_bit_cast(double2, fv[s]);
-        f[0] = d.x;
-        f[1] = d.y;
-      } else {
-        f[0] = (double)__uint_as_float(fv[s].x);
-        f[1] = (double)__uint_as_float(fv[s].y);
-        f[2] = (double)__uint_as_float(fv[s].z);
-        f[3] = (double)__uint_as_float(fv[s].w);
-      }
+      for (int s = 0; s < 4; ++s) {
+        double f[RPL];
+        if constexpr (RPL == 2) {
+          const double2 d = __builtin_bit_cast(double2, fv[s]);
+          f[0] = d.x;
+          f[1] = d.y;
+        } else {
+          f[0] = (double)__uint_as_float(fv[s].x);
+          f[1] = (double)__uint_as_float(fv[s].y);
+          f[2] = (double)__uint_as_float(fv[s].z);
+          f[3] = (double)__uint_as_float(fv[s].w);
+        }
 #pragma unroll
-      for (int v = 0; v < RPL; ++v) {
-        // (re, -im, ..) and (im, re, ..) of the complex pair this real belongs to
-        const double br = (v & 1) ? -f[v] : f[v];
-        const double bi = (v & 1) ? f[v - 1] : f[v + 1];
+        for (int v = 0; v < RPL; ++v) {
+          // (re, -im, ..) and (im, re, ..) of the complex pair this real belongs to
+          const double br = (v & 1) ? -f[v] : f[v];
+          const double bi = (v & 1) ? f[v - 1] : f[v + 1];
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-          const double xa = xs[16 * t + l16][RPL * (4 * s + g) + v];
-          re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, br, re[t], 0, 0, 0);
-          im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, bi, im[t], 0, 0, 0);
+          for (int t = 0; t < TB; ++t) {
+            const double xa = xs[16 * t + l16][RPL * (4 * s + g) + v];
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, br, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, bi, im[t], 0, 0, 0);
+          }
         }
       }
     }
@@ -1025,8 +1044,12 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
     const int64_t nwg = (int64_t)a.K * nbb * nrb;
     if (nwg <= 0) return hipSuccess;
     if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((gemm_fwd_f32_kernel<GEMM_FWD_NW, TB>), dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0, st, a,
-                       nbb, nrb);
+    if (a.Nd <= 8 * GEMM_FWD_NW)
+      hipLaunchKernelGGL((gemm_fwd_f32_kernel<GEMM_FWD_NW, TB, true>), dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0,
+                         st, a, nbb, nrb);
+    else
+      hipLaunchKernelGGL((gemm_fwd_f32_kernel<GEMM_FWD_NW, TB, false>), dim3((unsigned)nwg), dim3(64 * GEMM_FWD_NW), 0,
+                         st, a, nbb, nrb);
     return hipGetLastError();
   }
   const int nrb = (a.Nd + FWD_BN - 1) / FWD_BN;
@@ -1035,7 +1058,10 @@ static hipError_t gemm_fwd_go(int fdt, const GemvArgs& a, hipStream_t st) {
   if (nwg >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nwg), block(GEMM_THREADS);
   switch (fdt) {
-    case DT_F32: hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB>), grid, block, 0, st, a, nbb, nrb); break;
+    case DT_F32:
+      if (a.Nd <= FWD_BN / 2) hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB, true>), grid, block, 0, st, a, nbb, nrb);
+      else hipLaunchKernelGGL((gemm_fwd_x3_kernel<TB, false>), grid, block, 0, st, a, nbb, nrb);
+      break;
     case DT_F16:
       if (!a.x16) return hipErrorInvalidValue;  // the input of a 16-bit product is stored in 16 bits
       hipLaunchKernelGGL((gemm_fwd_h_kernel<s_f16, TB>), grid, block, 0, st, a, nbb, nrb);

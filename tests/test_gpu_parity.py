@@ -524,6 +524,40 @@ def test_gemm_path_vs_oracle(gpu, gemm_case, prec, nrhs):
     op.close()
 
 
+@pytest.mark.parametrize("Nd", [9, 24, 32])
+def test_gemm_few_sensors(gpu, Nd):
+    """Forward GEMM with at most 32 sensors, where half or more of each
+    workgroup's waves own only rows past Nd and skip their spectrum loads and
+    matrix-core work: every product kind and tile against the oracle and
+    against the one-vector path, every right-hand side checked."""
+    import torch
+    from paper_2508_10202_amd import Operator
+    s = Shape(64, Nd, 300, decay=50.0)
+    nrhs = 37
+    F, M, D = make_F(s, 95), make_m(s, 96, nrhs=nrhs), make_d(s, 97, nrhs=nrhs)
+    ref_d = oracle.forward(F, M)
+    op = Operator(torch.from_numpy(F).cuda(), spectra=("s", "b"), max_rhs=nrhs)
+    Mt = torch.from_numpy(M).cuda()
+    for prec in ("ddsdd", "dbbbd", "ddddd", "ddsdd+a64"):
+        op.set_precision(fwd=prec, adj=prec)
+        op.set_rhs_mode("gemv")
+        vd = op.matvec(Mt).cpu().numpy()
+        op.set_rhs_mode("gemm")
+        lo_f, hi_f = _gemm_bounds(prec, s.L, s.Nm)
+        kinds = (1, 2) if prec == "ddsdd" else (0,)
+        for tile in (16, 64):
+            for kind in kinds:
+                _say("case gemm few sensors", Nd, prec, "tile", tile, "kind", kind)
+                op.set_tuning(gemm_tile=(tile, tile), gemm_kind=(kind, kind))
+                gd = op.matvec(Mt).cpu().numpy()
+                e_f = _rel(gd, ref_d)
+                assert lo_f <= e_f <= hi_f, (prec, tile, kind, e_f)
+                for b in range(nrhs):
+                    assert _rel(gd[b], ref_d[b]) <= hi_f, (prec, tile, kind, b)
+                assert _rel(gd, vd) <= 2 * hi_f
+    op.close()
+
+
 def test_gemm_multi_rhs_shape(gpu):
     """Nt=512, Nd=128, Nm=4096 with 64 right-hand sides, FP32 and BF16 products on
     the matrix cores; four of the right-hand sides checked against the oracle."""
